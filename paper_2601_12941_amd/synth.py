@@ -1,0 +1,299 @@
+"""Seeded synthetic speckle image pairs with known displacement fields.
+
+This module is the input generator shared by the oracle tests, the GPU
+parity tests and the benchmark.  It holds none of the correlation method's
+arithmetic (no interpolation, no cost function, no solver): it only renders
+Gaussian-blob speckle, moves the blobs by an analytic field, adds noise and
+derives the region of interest and the ground truth at grid nodes.
+
+Blob model: I(x, y) = sum_k A_k exp(-((x-X_k)^2 + (y-Y_k)^2) / (2 s_k^2)),
+point-sampled at integer pixel centres (pixel (row i, col j) sits at x=j,
+y=i) and truncated at radius 5 s_k.  The deformed image renders the same
+blobs, unchanged in shape, at (X_k + u(X_k, Y_k), Y_k + v(X_k, Y_k)).  Noise
+is independent N(0, sigma_n) per image; integer images are rounded to the
+nearest integer and clipped to [0, 2^bits - 1].
+
+Random draws: numpy Generator(PCG64(seed)); blob draw order X, Y, sigma, A;
+each image's noise uses its own generator.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Callable, Optional
+
+import numpy as np
+
+Field = Callable[[np.ndarray, np.ndarray], tuple]
+
+
+# --------------------------------------------------------------------------
+# blob rendering
+# --------------------------------------------------------------------------
+def _render_blobs(W: int, H: int, X, Y, S, A, chunk_px: int = 1 << 23) -> np.ndarray:
+    """Sum of truncated Gaussian blobs sampled at integer pixel centres (float64)."""
+    img = np.zeros(W * H, dtype=np.float64)
+    X = np.asarray(X, np.float64)
+    Y = np.asarray(Y, np.float64)
+    S = np.asarray(S, np.float64)
+    A = np.asarray(A, np.float64)
+    if X.size == 0:
+        return img.reshape(H, W)
+    R = int(math.ceil(5.0 * float(S.max())))
+    off = np.arange(-R, R + 1, dtype=np.int64)
+    K = off.size
+    per = max(1, chunk_px // (K * K))
+    for b0 in range(0, X.size, per):
+        x = X[b0:b0 + per]
+        y = Y[b0:b0 + per]
+        s = S[b0:b0 + per]
+        a = A[b0:b0 + per]
+        cx = np.floor(x).astype(np.int64)
+        cy = np.floor(y).astype(np.int64)
+        px = cx[:, None] + off[None, :]                  # [b, K]
+        py = cy[:, None] + off[None, :]
+        dx2 = (px - x[:, None]) ** 2                       # [b, K]
+        dy2 = (py - y[:, None]) ** 2
+        inv = 1.0 / (2.0 * s * s)
+        r2 = dy2[:, :, None] + dx2[:, None, :]             # [b, K(y), K(x)]
+        val = a[:, None, None] * np.exp(-r2 * inv[:, None, None])
+        keep = r2 <= (25.0 * s * s)[:, None, None]
+        keep &= ((px >= 0) & (px < W))[:, None, :]
+        keep &= ((py >= 0) & (py < H))[:, :, None]
+        lin = py[:, :, None] * W + px[:, None, :]
+        img += np.bincount(lin[keep], weights=val[keep], minlength=W * H)
+    return img.reshape(H, W)
+
+
+def _finish(img: np.ndarray, noise_sigma: float, noise_seed: Optional[int], bits: Optional[int]):
+    out = img.copy()
+    if noise_sigma > 0 and noise_seed is not None:
+        rng = np.random.Generator(np.random.PCG64(noise_seed))
+        out += rng.normal(0.0, noise_sigma, size=out.shape)
+    if bits is None:
+        return out.astype(np.float32)
+    out = np.clip(np.rint(out), 0, (1 << bits) - 1)
+    return out.astype(np.uint8 if bits <= 8 else np.uint16)
+
+
+# --------------------------------------------------------------------------
+# displacement fields (absolute pixel coordinates)
+# --------------------------------------------------------------------------
+def field_affine(u0, v0, dudx=0.0, dudy=0.0, dvdx=0.0, dvdy=0.0, xc=0.0, yc=0.0) -> Field:
+    def f(x, y):
+        x = np.asarray(x, np.float64) - xc
+        y = np.asarray(y, np.float64) - yc
+        return u0 + dudx * x + dudy * y, v0 + dvdx * x + dvdy * y
+    f.grad = lambda x, y: (np.full_like(np.asarray(x, np.float64), dudx), np.full_like(np.asarray(x, np.float64), dudy),
+                           np.full_like(np.asarray(x, np.float64), dvdx), np.full_like(np.asarray(x, np.float64), dvdy))
+    return f
+
+
+def field_c1() -> Field:
+    """u = 1.37 + 0.002 x, v = -0.81 + 0.001 y."""
+    return field_affine(1.37, -0.81, dudx=0.002, dvdy=0.001)
+
+
+def field_sine(H: int, amp=0.5, lam0=10.0, lam1=300.0) -> Field:
+    """u = amp sin(2 pi x / lam(y)), lam(y) = lam0 + (lam1-lam0) y/(H-1), v = 0."""
+    def lam(y):
+        return lam0 + (lam1 - lam0) * np.asarray(y, np.float64) / (H - 1)
+
+    def f(x, y):
+        x = np.asarray(x, np.float64)
+        return amp * np.sin(2 * np.pi * x / lam(y)), np.zeros_like(x)
+
+    def grad(x, y):
+        x = np.asarray(x, np.float64)
+        L = lam(y)
+        ph = 2 * np.pi * x / L
+        dudx = amp * np.cos(ph) * 2 * np.pi / L
+        dudy = amp * np.cos(ph) * (-2 * np.pi * x / L ** 2) * (lam1 - lam0) / (H - 1)
+        z = np.zeros_like(x)
+        return dudx, dudy, z, z
+    f.grad = grad
+    return f
+
+
+def field_quadratic_c3(W: int, H: int) -> Field:
+    """Centred x~ = x - W/2, y~ = y - H/2:
+    u = 1e-5 x~^2 + 0.3 + 0.02 x~,  v = -2e-5 x~ y~ + 0.2 + 0.02 y~."""
+    xc, yc = W / 2.0, H / 2.0
+
+    def f(x, y):
+        xt = np.asarray(x, np.float64) - xc
+        yt = np.asarray(y, np.float64) - yc
+        return 1e-5 * xt * xt + 0.3 + 0.02 * xt, -2e-5 * xt * yt + 0.2 + 0.02 * yt
+
+    def grad(x, y):
+        xt = np.asarray(x, np.float64) - xc
+        yt = np.asarray(y, np.float64) - yc
+        return 2e-5 * xt + 0.02, np.zeros_like(xt), -2e-5 * yt, -2e-5 * xt + 0.02
+    f.grad = grad
+    return f
+
+
+def field_bump_c4(W: int, H: int, t=(3.41, -7.92), amp=0.8, width=4000.0) -> Field:
+    """(u, v) = (t_x + amp exp(-r^2 / (2 width^2)), t_y), r from the image centre."""
+    xc, yc = W / 2.0, H / 2.0
+
+    def f(x, y):
+        x = np.asarray(x, np.float64)
+        y = np.asarray(y, np.float64)
+        r2 = (x - xc) ** 2 + (y - yc) ** 2
+        return t[0] + amp * np.exp(-r2 / (2 * width * width)), np.full_like(x, t[1])
+
+    def grad(x, y):
+        x = np.asarray(x, np.float64)
+        y = np.asarray(y, np.float64)
+        r2 = (x - xc) ** 2 + (y - yc) ** 2
+        e = amp * np.exp(-r2 / (2 * width * width))
+        z = np.zeros_like(x)
+        return -e * (x - xc) / width ** 2, -e * (y - yc) / width ** 2, z, z
+    f.grad = grad
+    return f
+
+
+# --------------------------------------------------------------------------
+# pairs, ROI, grid, ground truth
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class Pair:
+    ref: np.ndarray
+    deformed: np.ndarray
+    roi: np.ndarray           # uint8 [H][W], 1 = inside
+    field: Field
+    bits: Optional[int]
+
+
+def draw_blobs(W, H, nblobs, sigma, amp, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    X = rng.uniform(0.0, W, nblobs)
+    Y = rng.uniform(0.0, H, nblobs)
+    S = rng.uniform(sigma[0], sigma[1], nblobs)
+    A = rng.uniform(amp[0], amp[1], nblobs)
+    return X, Y, S, A
+
+
+def roi_from_field(W: int, H: int, field: Field, margin: int = 4) -> np.ndarray:
+    """Pixels >= margin inside the image whose displaced position is also >= margin inside."""
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    u, v = field(xx, yy)
+    lo = margin
+    ok = (xx >= lo) & (xx <= W - 1 - lo) & (yy >= lo) & (yy <= H - 1 - lo)
+    ok &= (xx + u >= lo) & (xx + u <= W - 1 - lo) & (yy + v >= lo) & (yy + v <= H - 1 - lo)
+    return ok.astype(np.uint8)
+
+
+def make_pair(W, H, nblobs, sigma, amp, field: Field, noise_sigma, bits, seed_blobs,
+              seed_noise_ref, seed_noise_def, roi_margin=4) -> Pair:
+    X, Y, S, A = draw_blobs(W, H, nblobs, sigma, amp, seed_blobs)
+    ref = _render_blobs(W, H, X, Y, S, A)
+    u, v = field(X, Y)
+    de = _render_blobs(W, H, X + u, Y + v, S, A)
+    return Pair(_finish(ref, noise_sigma, seed_noise_ref, bits),
+                _finish(de, noise_sigma, seed_noise_def, bits),
+                roi_from_field(W, H, field, roi_margin), field, bits)
+
+
+def grid_shape(W, H, N, step):
+    """Nodes at x_c = h + i*step, i < nx = floor((W-N)/step)+1 (y likewise), h=(N-1)/2."""
+    nx = (W - N) // step + 1 if W >= N else 0
+    ny = (H - N) // step + 1 if H >= N else 0
+    return nx, ny
+
+
+def node_centres(W, H, N, step):
+    nx, ny = grid_shape(W, H, N, step)
+    h = (N - 1) // 2
+    xs = h + step * np.arange(nx)
+    ys = h + step * np.arange(ny)
+    return xs, ys
+
+
+def truth_at_nodes(field: Field, W, H, N, step):
+    """Ground-truth (u, v, du/dx, du/dy, dv/dx, dv/dy) at every node centre, [ny][nx] arrays."""
+    xs, ys = node_centres(W, H, N, step)
+    X, Y = np.meshgrid(xs.astype(np.float64), ys.astype(np.float64))
+    u, v = field(X, Y)
+    g = field.grad(X, Y) if hasattr(field, "grad") else (None,) * 4
+    return u, v, g
+
+
+# --------------------------------------------------------------------------
+# the workloads (sizes, speckle statistics and fields as specified per config)
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class Workload:
+    name: str
+    W: int
+    H: int
+    bits: int
+    nblobs: int
+    sigma: tuple
+    amp: tuple
+    noise: float
+    N: int
+    step: int
+    shape: int
+    tol: float
+    max_iter: int
+    zncc_min: float
+    seed_radius: int
+    seeds: list               # [(x, y, u0, v0)]
+    seed_blobs: int
+    seed_noise_ref: int
+    seed_noise_def: int
+    field_name: str
+
+    def field(self) -> Field:
+        if self.field_name == "c1":
+            return field_c1()
+        if self.field_name == "sine":
+            return field_sine(self.H)
+        if self.field_name == "quad":
+            return field_quadratic_c3(self.W, self.H)
+        if self.field_name == "bump":
+            return field_bump_c4(self.W, self.H)
+        raise ValueError(self.field_name)
+
+    def pair(self) -> Pair:
+        return make_pair(self.W, self.H, self.nblobs, self.sigma, self.amp, self.field(), self.noise,
+                         self.bits, self.seed_blobs, self.seed_noise_ref, self.seed_noise_def)
+
+    def params(self) -> dict:
+        return dict(subset_size=self.N, step=self.step, shape=self.shape, tol=self.tol,
+                    max_iter=self.max_iter, zncc_min=self.zncc_min, seed_radius=self.seed_radius)
+
+
+def workload(name: str, size: Optional[int] = None, **over) -> Workload:
+    """Named workloads.  `size` shrinks the image (blob count scaled to keep the density)."""
+    if name == "c1":        # 512^2 u8 speckle, affine field, subset 21 step 5
+        W = size or 512
+        d = dict(name="c1", W=W, H=W, bits=8, nblobs=int(round(3000 * W * W / 512 ** 2)), sigma=(2.0, 4.0),
+                 amp=(60.0, 200.0), noise=2.0, N=21, step=5, shape=6, tol=1e-4, max_iter=50, zncc_min=0.7,
+                 seed_radius=8, seeds=[(W / 2, W / 2, 0.0, 0.0)], seed_blobs=1001, seed_noise_ref=1002,
+                 seed_noise_def=1003, field_name="c1")
+    elif name == "c2":      # 2048^2 12-bit speckle, sinusoidal u, subset 31 step 2
+        W = size or 2048
+        d = dict(name="c2", W=W, H=W, bits=12, nblobs=int(round(48000 * W * W / 2048 ** 2)), sigma=(2.0, 4.0),
+                 amp=(960.0, 3200.0), noise=4.0, N=31, step=2, shape=6, tol=1e-4, max_iter=50, zncc_min=0.7,
+                 seed_radius=4, seeds=[(W / 2, W / 2, 0.0, 0.0)], seed_blobs=2001, seed_noise_ref=2002,
+                 seed_noise_def=2003, field_name="sine")
+    elif name == "c3":      # 4096^2 u8 speckle, quadratic field + 2 % strain, subsets 21/41 step 4
+        W = size or 4096
+        d = dict(name="c3", W=W, H=W, bits=8, nblobs=int(round(192000 * W * W / 4096 ** 2)), sigma=(2.0, 4.0),
+                 amp=(60.0, 200.0), noise=2.0, N=21, step=4, shape=6, tol=1e-4, max_iter=50, zncc_min=0.7,
+                 seed_radius=4, seeds=[(W / 2, W / 2, 0.3, 0.2)], seed_blobs=3001, seed_noise_ref=3002,
+                 seed_noise_def=3003, field_name="quad")
+    elif name == "c4":      # 32768^2 u8 speckle, rigid shift + Gaussian bump, subset 41 step 20, 16 seeds
+        W = size or 32768
+        seeds = [((i + 0.5) * W / 4, (j + 0.5) * W / 4, 3.41, -7.92) for j in range(4) for i in range(4)]
+        d = dict(name="c4", W=W, H=W, bits=8, nblobs=int(round(0.02 * W * W)), sigma=(1.5, 3.0),
+                 amp=(60.0, 200.0), noise=2.0, N=41, step=20, shape=6, tol=1e-4, max_iter=50, zncc_min=0.7,
+                 seed_radius=12, seeds=seeds, seed_blobs=4001, seed_noise_ref=4002, seed_noise_def=4003,
+                 field_name="bump")
+    else:
+        raise ValueError(name)
+    d.update(over)
+    return Workload(**d)
