@@ -1,0 +1,179 @@
+/*
+ * dic.h -- C ABI of the MI355X (gfx950) reliability-guided 2D digital image
+ * correlation library.
+ *
+ * The library computes, for every node of a regular grid of square subsets
+ * inside a region of interest, the shape-function parameters that map the
+ * reference subset onto the deformed image (Hirst et al., arXiv 2601.12941,
+ * Sec. 2.2): cubic B-spline gray-level interpolation, the zero-normalised
+ * sum of squared differences of Eq. (4) as the cost, the affine or quadratic
+ * shape function of Eq. (5) (parameters p0..p11 in that equation's order),
+ * per-subset inverse-compositional Gauss-Newton minimisation, and
+ * reliability-guided propagation of initial guesses from a seed to
+ * 4-neighbours (Sec. 2.4), processed as breadth-first frontier waves.
+ *
+ * Conventions
+ *   - Pixel (row i, column j) sits at x = j, y = i.  Nodes sit at
+ *     x_c = h + i*step (i < nx = floor((W-N)/step)+1), y likewise, with
+ *     h = (N-1)/2; result arrays are row-major [ny][nx].
+ *   - Every image, mask and result pointer is DEVICE memory on the context's
+ *     device, owned by the caller.  Seeds are a HOST array.
+ *   - All work is ordered on the context's HIP stream; every call that
+ *     launches work returns after it has completed.
+ *   - Errors: negative dic_status, with a message in dic_last_error().  After
+ *     DIC_E_INVAL, DIC_E_NOSEED or DIC_E_UNSUPPORTED the context stays usable;
+ *     after DIC_E_DEVICE it must be destroyed.  Output contents are undefined
+ *     after any error.
+ *   - One context must not be used from two host threads at once.
+ */
+#ifndef DIC_H
+#define DIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dic_ctx dic_ctx; /* opaque: owns the reference precompute and all scratch */
+
+typedef enum {
+    DIC_OK = 0,
+    DIC_E_INVAL = -1,       /* bad argument, size or call order inside one call */
+    DIC_E_NOMEM = -2,       /* device allocation failed */
+    DIC_E_DEVICE = -3,      /* HIP runtime or kernel error */
+    DIC_E_STATE = -4,       /* dic_correlate before dic_set_reference */
+    DIC_E_NOSEED = -5,      /* no seed lies on an active node */
+    DIC_E_UNSUPPORTED = -6  /* valid but not built (e.g. rigid shape) */
+} dic_status;
+
+typedef enum { DIC_PIX_U8 = 0, DIC_PIX_U16 = 1, DIC_PIX_F32 = 2 } dic_pixel;
+
+/* Shape functions of Eq. (5); the value is the parameter count. */
+typedef enum { DIC_SHAPE_RIGID = 2, DIC_SHAPE_AFFINE = 6, DIC_SHAPE_QUADRATIC = 12 } dic_shape;
+
+/* Per-node status codes (dic_result.status). */
+enum {
+    DIC_NODE_CONVERGED = 0,     /* increment norm below tol and ZNCC >= zncc_min */
+    DIC_NODE_NOT_REACHED = 1,   /* active but never given a guess by propagation */
+    DIC_NODE_NOT_IN_ROI = 2,    /* some subset pixel outside the ROI mask */
+    DIC_NODE_MAX_ITER = 3,      /* max_iter iterations without convergence */
+    DIC_NODE_LOW_ZNCC = 4,      /* converged with ZNCC < zncc_min */
+    DIC_NODE_OUT_OF_BOUNDS = 5, /* a warped pixel left [0, W-1] x [0, H-1] */
+    DIC_NODE_FLAT_REF = 6,      /* reference subset RMS deviation < 1e-6 of its mean level */
+    DIC_NODE_FLAT_DEF = 7,      /* same for the warped deformed subset */
+    DIC_NODE_SINGULAR = 8,      /* Gauss-Newton Hessian not positive definite */
+    DIC_NODE_NAN = 9            /* NaN in the data or the iteration */
+};
+
+/* A 2-D image in device memory. */
+typedef struct {
+    int32_t width, height;
+    int64_t pitch_bytes;  /* distance between rows, >= width * pixel size */
+    int32_t pixel;        /* dic_pixel */
+    const void *data;     /* DEVICE pointer to row 0 */
+} dic_image;
+
+/* Correlation parameters (Listing 1's subset size / step, Sec. 2.2's
+ * convergence threshold and iteration cap, Eq. (5)'s shape function). */
+typedef struct {
+    int32_t subset_size;        /* N: odd, 5 <= N <= 63 */
+    int32_t step;               /* grid step in pixels, >= 1 */
+    int32_t shape;              /* DIC_SHAPE_AFFINE or DIC_SHAPE_QUADRATIC */
+    int32_t max_iter;           /* >= 1 */
+    double tol;                 /* convergence threshold on |dp| in pixels (see dic_correlate) */
+    double zncc_min;            /* a converged subset with lower ZNCC is LOW_ZNCC and does not propagate */
+    int32_t seed_radius;        /* integer search radius R of the seed initialisation, 0..64 */
+    int32_t guess_mode;         /* 0: extrapolate the neighbour's shape function, 1: copy it */
+    int32_t coef_fp16;          /* 1: deformed-image spline coefficients stored as FP16 */
+    int32_t reduce_fp64;        /* 1: cross-lane sums and the normal-equation solve in FP64; 0: FP32 */
+    int32_t nan_unconverged;    /* 1: write NaN into p of every node that is not CONVERGED */
+    int32_t threads_per_subset; /* 0 = automatic; else 64, 128 or 256 */
+} dic_params;
+
+/* A seed: a point near which propagation starts (snapped to the nearest
+ * active node) and a guess (u0, v0) for the centre of its integer search. */
+typedef struct {
+    double x, y, u0, v0;
+} dic_seed;
+
+/* Caller-allocated DEVICE result arrays, each [ny][nx] row-major (p is
+ * [shape][ny][nx]: plane k holds parameter p_k of Eq. (5)). */
+typedef struct {
+    float *p;
+    float *zncc;      /* zero-normalised cross-correlation 1 - ZNSSD/2 at the last evaluated p */
+    int16_t *iters;   /* IC-GN iterations performed (0 if never computed) */
+    int8_t *status;   /* DIC_NODE_* */
+    int32_t *wave;    /* frontier wave that computed the node (0 = seed), -1 if never computed */
+} dic_result;
+
+typedef struct {
+    int64_t nodes;          /* nx * ny */
+    int64_t active;         /* nodes whose subset lies inside the ROI */
+    int64_t computed;       /* nodes on which IC-GN ran (all frames of the last call) */
+    int64_t converged;      /* CONVERGED nodes (all frames of the last call) */
+    int64_t iterations;     /* total IC-GN iterations (all frames of the last call) */
+    int32_t waves;          /* frontier waves launched by the last call */
+    int32_t frames;         /* frames in the last call */
+    int32_t threads_per_subset;
+    int32_t seed_du, seed_dv; /* integer seed shift of the first seed of the last frame */
+    double ms_total;        /* device time of the last call (HIP events) */
+    double ms_icgn;         /* device time inside the IC-GN wave kernels */
+    double ms_prefilter;    /* device time of the deformed-image prefilter */
+} dic_stats;
+
+/* Create a context on HIP device `device`, ordering its work on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  *out receives the context. */
+dic_status dic_create(dic_ctx **out, int device, void *hip_stream);
+
+/*
+ * Set (or replace) the reference image, ROI and parameters.  Computes and
+ * keeps resident: the reference spline coefficients (Sec. 2.2), the
+ * reference intensities and gradients at every pixel, and per node the
+ * subset mean and norm, the Gauss-Newton Hessian's inverse and the sums the
+ * iteration reuses.  roi_mask_dev: DEVICE uint8 [height][width] (pitch =
+ * width), nonzero = inside; NULL = whole image.  A node is active iff all N^2
+ * of its pixels are inside.
+ */
+dic_status dic_set_reference(dic_ctx *c, const dic_image *ref, const uint8_t *roi_mask_dev, const dic_params *prm);
+
+/* Grid of the current reference: nx, ny, the first node centre (x0, y0) and
+ * the step.  Any pointer may be NULL. */
+dic_status dic_grid_shape(const dic_ctx *c, int32_t *nx, int32_t *ny, int32_t *x0, int32_t *y0, int32_t *step);
+
+/*
+ * Correlate one deformed image (same size as the reference) from `nseeds`
+ * host seeds; results go to `out` (device arrays, [ny][nx]).
+ * Per node: inverse-compositional Gauss-Newton on ZNSSD (Eq. (4)) until the
+ * increment norm sqrt(dp0^2 + dp1^2 + h^2 sum_{2..5} dpj^2 + h^4 sum_{6..11}
+ * dpj^2) < tol, or max_iter.  Seeds: integer ZNCC search over
+ * round(u0, v0) + [-R, R]^2, then IC-GN.  Propagation: wave k+1 holds every
+ * active, unvisited node with a CONVERGED 4-neighbour in wave k, started from
+ * the guess of the neighbour with the largest ZNCC (exact ties: left, right,
+ * up, down).  Returns DIC_E_NOSEED if no seed reaches an active node.
+ */
+dic_status dic_correlate(dic_ctx *c, const dic_image *def, const dic_seed *seeds, int32_t nseeds, dic_result *out);
+
+/*
+ * Correlate `nframes` deformed images against the same reference in one
+ * batched pass: every frontier wave of every frame goes into one launch.
+ * seeds: nframes * nseeds host seeds (frame-major); outs: nframes results.
+ * Each frame's results equal those of dic_correlate on that frame alone.
+ */
+dic_status dic_correlate_batch(dic_ctx *c, const dic_image *defs, int32_t nframes, const dic_seed *seeds,
+                               int32_t nseeds, dic_result *outs);
+
+/* Counters and timings of the last call. */
+dic_status dic_get_stats(const dic_ctx *c, dic_stats *out);
+
+/* Release the context and everything it owns. */
+dic_status dic_destroy(dic_ctx *c);
+
+/* Message of the last error on this context ("" if none); valid until the next call. */
+const char *dic_last_error(const dic_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DIC_H */

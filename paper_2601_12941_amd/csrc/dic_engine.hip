@@ -1,0 +1,527 @@
+// Host engine and C ABI of the reliability-guided DIC library (include/dic.h).
+//
+// The context owns every device buffer of the path: the resident reference
+// precompute (coefficients, per-pixel intensity and gradient, per-node
+// Hessian inverse and sums), and per-frame scratch (deformed coefficients,
+// frontier lists, parent keys).  Caller-owned result arrays double as the
+// propagation state: a node's p, read by its children in the next wave, is
+// the p it reports.
+//
+// Wave loop: waves are launched back to back on the context's stream; the
+// host reads the size of the next wave only once per chunk of waves (the
+// chunk doubles up to 64), so host synchronisation is amortised; waves
+// launched past the end of propagation find an empty frontier and exit.
+#include "../../include/dic.h"
+#include "dic_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace dicmi;
+
+namespace {
+
+struct FrameBuf {
+    void *dcoef_base = nullptr;  // padded deformed coefficients
+    uint64_t *pkey = nullptr;
+    int32_t *list0 = nullptr, *list1 = nullptr, *counts = nullptr;
+    double *seed_p = nullptr;
+    int32_t *seed_nodes = nullptr;
+    unsigned long long *stat = nullptr;
+};
+
+size_t pixel_size(int pixel) { return pixel == DIC_PIX_U8 ? 1 : (pixel == DIC_PIX_U16 ? 2 : 4); }
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+} // namespace
+
+struct dic_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    bool has_ref = false;
+    dic_params prm{};
+    int W = 0, H = 0, nx = 0, ny = 0, np = 6, tps = 64;
+    int64_t nodes = 0, active = 0;
+    int ref_pixel = 0;
+
+    float *ref_coef_base = nullptr;
+    int64_t cpitch = 0;            // coefficient row pitch (elements)
+    float *pf = nullptr, *pfx = nullptr, *pfy = nullptr;
+    int64_t ppitch = 0;
+    double *cache = nullptr;
+    int8_t *flag = nullptr;
+    void *ref_raw = nullptr;
+    float *tmp = nullptr;          // prefilter row-pass scratch
+    int64_t tpitch = 0;
+    std::vector<int8_t> flag_host;
+
+    std::vector<FrameBuf> frames;
+    FrameState *d_frames = nullptr;
+    std::vector<FrameState> h_frames;
+    int32_t *d_centre = nullptr;
+    double *d_zbuf = nullptr;
+    int zbuf_capacity = 0, centre_capacity = 0;
+    int32_t *d_wave_total = nullptr;
+    int32_t *h_pinned = nullptr;
+    hipEvent_t ev[4] = {};
+    dic_stats stats{};
+
+    size_t coef_elems() const { return static_cast<size_t>(cpitch) * (H + 2 * kPad); }
+
+    RefView view() const
+    {
+        RefView R;
+        R.coef = ref_coef_base + kPad * cpitch + kPad;
+        R.cpitch = cpitch;
+        R.pf = pf;
+        R.pfx = pfx;
+        R.pfy = pfy;
+        R.ppitch = ppitch;
+        R.cache = cache;
+        R.flag = flag;
+        R.raw = ref_raw;
+        R.pixel = ref_pixel;
+        R.W = W;
+        R.H = H;
+        R.N = prm.subset_size;
+        R.step = prm.step;
+        R.nx = nx;
+        R.ny = ny;
+        R.nodes = nodes;
+        return R;
+    }
+};
+
+#define FAIL(code, ...)                                                                                               \
+    do {                                                                                                              \
+        char buf_[512];                                                                                               \
+        snprintf(buf_, sizeof(buf_), __VA_ARGS__);                                                                    \
+        c->err = buf_;                                                                                                \
+        return code;                                                                                                  \
+    } while (0)
+
+#define HIPCHK(expr)                                                                                                  \
+    do {                                                                                                              \
+        hipError_t e_ = (expr);                                                                                       \
+        if (e_ != hipSuccess) {                                                                                       \
+            if (e_ == hipErrorOutOfMemory) FAIL(DIC_E_NOMEM, "%s: %s", #expr, hipGetErrorString(e_));               \
+            FAIL(DIC_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));                                              \
+        }                                                                                                             \
+    } while (0)
+
+namespace {
+
+template <typename T> void dfree(T *&p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+void free_reference(dic_ctx *c)
+{
+    dfree(c->ref_coef_base);
+    dfree(c->pf);
+    dfree(c->pfx);
+    dfree(c->pfy);
+    dfree(c->cache);
+    dfree(c->flag);
+    dfree(c->ref_raw);
+    dfree(c->tmp);
+    dfree(c->d_wave_total);
+    for (auto &f : c->frames) {
+        dfree(f.dcoef_base);
+        dfree(f.pkey);
+        dfree(f.list0);
+        dfree(f.list1);
+        dfree(f.counts);
+        dfree(f.seed_p);
+        dfree(f.seed_nodes);
+        dfree(f.stat);
+    }
+    c->frames.clear();
+    c->has_ref = false;
+}
+
+dic_status check_image(dic_ctx *c, const dic_image *im, const char *what)
+{
+    if (!im) FAIL(DIC_E_INVAL, "%s image is NULL", what);
+    if (!im->data) FAIL(DIC_E_INVAL, "%s image data is NULL", what);
+    if (im->pixel < DIC_PIX_U8 || im->pixel > DIC_PIX_F32) FAIL(DIC_E_INVAL, "%s pixel type %d", what, im->pixel);
+    if (im->width < 1 || im->height < 1) FAIL(DIC_E_INVAL, "%s size %dx%d", what, im->width, im->height);
+    if (im->pitch_bytes < static_cast<int64_t>(im->width * pixel_size(im->pixel)))
+        FAIL(DIC_E_INVAL, "%s pitch %lld below row size", what, static_cast<long long>(im->pitch_bytes));
+    return DIC_OK;
+}
+
+// Ensure per-frame scratch for `n` frames.
+dic_status ensure_frames(dic_ctx *c, int n)
+{
+    const int np = c->np;
+    const bool half = c->prm.coef_fp16 != 0;
+    while (static_cast<int>(c->frames.size()) < n) {
+        FrameBuf f;
+        HIPCHK(hipMalloc(&f.dcoef_base, c->coef_elems() * (half ? sizeof(__half) : sizeof(float))));
+        HIPCHK(hipMalloc(&f.pkey, sizeof(uint64_t) * c->nodes));
+        HIPCHK(hipMalloc(&f.list0, sizeof(int32_t) * c->nodes));
+        HIPCHK(hipMalloc(&f.list1, sizeof(int32_t) * c->nodes));
+        HIPCHK(hipMalloc(&f.counts, sizeof(int32_t) * (c->nodes + 2)));
+        HIPCHK(hipMalloc(&f.stat, sizeof(unsigned long long) * 4));
+        f.seed_p = nullptr;
+        f.seed_nodes = nullptr;
+        c->frames.push_back(f);
+    }
+    (void)np;
+    if (!c->d_frames) HIPCHK(hipMalloc(&c->d_frames, sizeof(FrameState) * kMaxFrames));
+    return DIC_OK;
+}
+
+// Nearest active node to (x, y), ties to smaller y then smaller x; -1 if none.
+int64_t snap_seed(const dic_ctx *c, double x, double y)
+{
+    const int h = (c->prm.subset_size - 1) / 2, s = c->prm.step;
+    int64_t best = -1;
+    double bd = 0.0;
+    for (int j = 0; j < c->ny; ++j)
+        for (int i = 0; i < c->nx; ++i) {
+            const int64_t node = static_cast<int64_t>(j) * c->nx + i;
+            if (c->flag_host[node] < 0) continue;
+            const double dx = h + i * s - x, dy = h + j * s - y;
+            const double d = dx * dx + dy * dy;
+            if (best < 0 || d < bd) {
+                best = node;
+                bd = d;
+            }
+        }
+    return best;
+}
+
+} // namespace
+
+extern "C" {
+
+dic_status dic_create(dic_ctx **out, int device, void *hip_stream)
+{
+    if (!out) return DIC_E_INVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return DIC_E_DEVICE;
+    if (device < 0 || device >= ndev) return DIC_E_INVAL;
+    if (hipSetDevice(device) != hipSuccess) return DIC_E_DEVICE;
+    dic_ctx *c = new dic_ctx();
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    for (auto &e : c->ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            delete c;
+            return DIC_E_DEVICE;
+        }
+    if (hipHostMalloc(reinterpret_cast<void **>(&c->h_pinned), 64 * sizeof(int32_t)) != hipSuccess) {
+        delete c;
+        return DIC_E_DEVICE;
+    }
+    *out = c;
+    return DIC_OK;
+}
+
+const char *dic_last_error(const dic_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+dic_status dic_destroy(dic_ctx *c)
+{
+    if (!c) return DIC_E_INVAL;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    free_reference(c);
+    dfree(c->d_frames);
+    dfree(c->d_centre);
+    dfree(c->d_zbuf);
+    if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+    for (auto &e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete c;
+    return DIC_OK;
+}
+
+dic_status dic_grid_shape(const dic_ctx *c, int32_t *nx, int32_t *ny, int32_t *x0, int32_t *y0, int32_t *step)
+{
+    if (!c) return DIC_E_INVAL;
+    if (!c->has_ref) return DIC_E_STATE;
+    const int h = (c->prm.subset_size - 1) / 2;
+    if (nx) *nx = c->nx;
+    if (ny) *ny = c->ny;
+    if (x0) *x0 = h;
+    if (y0) *y0 = h;
+    if (step) *step = c->prm.step;
+    return DIC_OK;
+}
+
+dic_status dic_get_stats(const dic_ctx *c, dic_stats *out)
+{
+    if (!c || !out) return DIC_E_INVAL;
+    *out = c->stats;
+    return DIC_OK;
+}
+
+dic_status dic_set_reference(dic_ctx *c, const dic_image *ref, const uint8_t *roi_mask_dev, const dic_params *prm)
+{
+    if (!c) return DIC_E_INVAL;
+    c->err.clear();
+    if (!prm) FAIL(DIC_E_INVAL, "params is NULL");
+    dic_status st = check_image(c, ref, "reference");
+    if (st != DIC_OK) return st;
+    const dic_params p = *prm;
+    if (p.subset_size < 5 || p.subset_size > 63 || (p.subset_size & 1) == 0)
+        FAIL(DIC_E_INVAL, "subset_size %d (odd, 5..63)", p.subset_size);
+    if (p.step < 1) FAIL(DIC_E_INVAL, "step %d", p.step);
+    if (p.shape == DIC_SHAPE_RIGID) FAIL(DIC_E_UNSUPPORTED, "rigid shape function is not built");
+    if (p.shape != DIC_SHAPE_AFFINE && p.shape != DIC_SHAPE_QUADRATIC) FAIL(DIC_E_INVAL, "shape %d", p.shape);
+    if (p.max_iter < 1 || p.max_iter > 32767) FAIL(DIC_E_INVAL, "max_iter %d", p.max_iter);
+    if (!(p.tol > 0.0) || !std::isfinite(p.tol)) FAIL(DIC_E_INVAL, "tol %g", p.tol);
+    if (!std::isfinite(p.zncc_min)) FAIL(DIC_E_INVAL, "zncc_min %g", p.zncc_min);
+    if (p.seed_radius < 0 || p.seed_radius > 64) FAIL(DIC_E_INVAL, "seed_radius %d", p.seed_radius);
+    if (p.guess_mode != 0 && p.guess_mode != 1) FAIL(DIC_E_INVAL, "guess_mode %d", p.guess_mode);
+    if (ref->width < p.subset_size || ref->height < p.subset_size)
+        FAIL(DIC_E_INVAL, "image %dx%d smaller than subset %d", ref->width, ref->height, p.subset_size);
+    int tps = p.threads_per_subset;
+    if (tps == 0) tps = p.subset_size <= 21 ? 64 : (p.subset_size <= 45 ? 128 : 256);
+    if (!supported_tps(p.subset_size, tps))
+        FAIL(DIC_E_INVAL, "threads_per_subset %d unsupported for subset %d", tps, p.subset_size);
+    if (p.shape == DIC_SHAPE_QUADRATIC && tps == 64 && p.subset_size > 21)
+        FAIL(DIC_E_UNSUPPORTED, "quadratic shape with 64 threads is built for subsets up to 21");
+
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize());
+    free_reference(c);
+    c->prm = p;
+    c->prm.threads_per_subset = tps;
+    c->tps = tps;
+    c->np = p.shape;
+    c->W = ref->width;
+    c->H = ref->height;
+    c->nx = (c->W - p.subset_size) / p.step + 1;
+    c->ny = (c->H - p.subset_size) / p.step + 1;
+    c->nodes = static_cast<int64_t>(c->nx) * c->ny;
+    c->ref_pixel = ref->pixel;
+    c->cpitch = round_up(c->W + 2 * kPad, 64);
+    c->ppitch = round_up(c->W, 64);
+    c->tpitch = round_up(c->W, 64);
+    hipStream_t s = c->stream;
+
+    HIPCHK(hipMalloc(&c->ref_coef_base, c->coef_elems() * sizeof(float)));
+    HIPCHK(hipMalloc(&c->tmp, sizeof(float) * c->tpitch * c->H));
+    HIPCHK(hipMalloc(&c->pf, sizeof(float) * c->ppitch * c->H));
+    HIPCHK(hipMalloc(&c->pfx, sizeof(float) * c->ppitch * c->H));
+    HIPCHK(hipMalloc(&c->pfy, sizeof(float) * c->ppitch * c->H));
+    HIPCHK(hipMalloc(&c->cache, sizeof(double) * cache_slots(c->np) * c->nodes));
+    HIPCHK(hipMalloc(&c->flag, c->nodes));
+    const size_t rowb = c->W * pixel_size(ref->pixel);
+    HIPCHK(hipMalloc(&c->ref_raw, rowb * c->H));
+    HIPCHK(hipMalloc(&c->d_wave_total, sizeof(int32_t) * (c->nodes + 130)));
+    HIPCHK(hipMemcpy2DAsync(c->ref_raw, rowb, ref->data, ref->pitch_bytes, rowb, c->H, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemsetAsync(c->cache, 0, sizeof(double) * cache_slots(c->np) * c->nodes, s));
+
+    RefView R = c->view();
+    launch_prefilter(ref->data, ref->pitch_bytes, ref->pixel, c->W, c->H, c->tmp, c->tpitch, const_cast<float *>(R.coef),
+                     c->cpitch, false, s);
+    launch_ref_pixels(R, c->pf, c->pfx, c->pfy, s);
+    launch_active(roi_mask_dev, R, c->flag, s);
+    launch_ref_nodes(R, c->np, tps, c->cache, c->flag, s);
+    HIPCHK(hipGetLastError());
+    c->flag_host.resize(c->nodes);
+    HIPCHK(hipMemcpyAsync(c->flag_host.data(), c->flag, c->nodes, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    c->active = 0;
+    for (int64_t i = 0; i < c->nodes; ++i) c->active += c->flag_host[i] >= 0;
+    c->has_ref = true;
+    c->stats = dic_stats{};
+    c->stats.nodes = c->nodes;
+    c->stats.active = c->active;
+    c->stats.threads_per_subset = tps;
+    return DIC_OK;
+}
+
+dic_status dic_correlate_batch(dic_ctx *c, const dic_image *defs, int32_t nframes, const dic_seed *seeds,
+                               int32_t nseeds, dic_result *outs)
+{
+    if (!c) return DIC_E_INVAL;
+    c->err.clear();
+    if (!c->has_ref) FAIL(DIC_E_STATE, "dic_correlate before dic_set_reference");
+    if (nframes < 1 || nframes > kMaxFrames) FAIL(DIC_E_INVAL, "nframes %d (1..%d)", nframes, kMaxFrames);
+    if (!defs || !outs) FAIL(DIC_E_INVAL, "NULL images or results");
+    if (nseeds < 1 || !seeds) FAIL(DIC_E_INVAL, "no seeds");
+    for (int f = 0; f < nframes; ++f) {
+        dic_status st = check_image(c, defs + f, "deformed");
+        if (st != DIC_OK) return st;
+        if (defs[f].width != c->W || defs[f].height != c->H)
+            FAIL(DIC_E_INVAL, "deformed image %d is %dx%d, reference is %dx%d", f, defs[f].width, defs[f].height, c->W,
+                 c->H);
+        if (!outs[f].p || !outs[f].zncc || !outs[f].iters || !outs[f].status || !outs[f].wave)
+            FAIL(DIC_E_INVAL, "result %d has a NULL array", f);
+    }
+    for (int q = 0; q < nframes * nseeds; ++q)
+        if (!std::isfinite(seeds[q].x) || !std::isfinite(seeds[q].y) || !std::isfinite(seeds[q].u0) ||
+            !std::isfinite(seeds[q].v0))
+            FAIL(DIC_E_INVAL, "seed %d is not finite", q);
+
+    HIPCHK(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    dic_status st = ensure_frames(c, nframes);
+    if (st != DIC_OK) return st;
+
+    // seeds: snap to active nodes, de-duplicate per frame, integer search centre
+    std::vector<int32_t> seed_nodes(static_cast<size_t>(nframes) * nseeds), centre(2 * nframes * nseeds);
+    std::vector<int> nuniq(nframes, 0);
+    for (int f = 0; f < nframes; ++f) {
+        for (int q = 0; q < nseeds; ++q) {
+            const dic_seed &sd = seeds[f * nseeds + q];
+            const int64_t node = snap_seed(c, sd.x, sd.y);
+            if (node < 0) continue;
+            bool dup = false;
+            for (int r = 0; r < nuniq[f]; ++r) dup = dup || seed_nodes[f * nseeds + r] == node;
+            if (dup) continue;
+            const int u = nuniq[f]++;
+            seed_nodes[f * nseeds + u] = static_cast<int32_t>(node);
+            centre[2 * (f * nseeds + u)] = static_cast<int32_t>(std::lround(sd.u0));
+            centre[2 * (f * nseeds + u) + 1] = static_cast<int32_t>(std::lround(sd.v0));
+        }
+        if (nuniq[f] == 0) FAIL(DIC_E_NOSEED, "frame %d: no seed lies on an active node", f);
+    }
+    const int side = 2 * c->prm.seed_radius + 1;
+    const int need_z = nframes * nseeds * side * side;
+    if (need_z > c->zbuf_capacity) {
+        dfree(c->d_zbuf);
+        HIPCHK(hipMalloc(&c->d_zbuf, sizeof(double) * need_z));
+        c->zbuf_capacity = need_z;
+    }
+    if (2 * nframes * nseeds > c->centre_capacity) {
+        dfree(c->d_centre);
+        HIPCHK(hipMalloc(&c->d_centre, sizeof(int32_t) * 2 * nframes * nseeds));
+        c->centre_capacity = 2 * nframes * nseeds;
+    }
+    for (int f = 0; f < nframes; ++f) {
+        FrameBuf &fb = c->frames[f];
+        dfree(fb.seed_p);
+        dfree(fb.seed_nodes);
+        HIPCHK(hipMalloc(&fb.seed_p, sizeof(double) * 2 * nseeds));
+        HIPCHK(hipMalloc(&fb.seed_nodes, sizeof(int32_t) * nseeds));
+    }
+
+    const bool half = c->prm.coef_fp16 != 0;
+    RefView R = c->view();
+    HIPCHK(hipEventRecord(c->ev[0], s));
+    c->h_frames.resize(nframes);
+    for (int f = 0; f < nframes; ++f) {
+        FrameBuf &fb = c->frames[f];
+        FrameState &F = c->h_frames[f];
+        const size_t esz = half ? sizeof(__half) : sizeof(float);
+        F.dcoef = static_cast<char *>(fb.dcoef_base) + (kPad * c->cpitch + kPad) * esz;
+        F.dpitch = c->cpitch;
+        F.draw = defs[f].data;
+        F.draw_pitch = defs[f].pitch_bytes;
+        F.dpixel = defs[f].pixel;
+        F.p = outs[f].p;
+        F.zncc = outs[f].zncc;
+        F.iters = outs[f].iters;
+        F.status = outs[f].status;
+        F.wave = outs[f].wave;
+        F.pkey = fb.pkey;
+        F.list0 = fb.list0;
+        F.list1 = fb.list1;
+        F.counts = fb.counts;
+        F.seed_p = fb.seed_p;
+        F.seed_nodes = fb.seed_nodes;
+        F.nseeds = nuniq[f];
+        F.stat = fb.stat;
+        launch_prefilter(defs[f].data, defs[f].pitch_bytes, defs[f].pixel, c->W, c->H, c->tmp, c->tpitch,
+                         const_cast<void *>(F.dcoef), c->cpitch, half, s);
+        launch_init_frame(R, F, c->np, s);
+        HIPCHK(hipMemsetAsync(fb.stat, 0, sizeof(unsigned long long) * 4, s));
+        HIPCHK(hipMemcpyAsync(fb.seed_nodes, seed_nodes.data() + f * nseeds, sizeof(int32_t) * nseeds,
+                              hipMemcpyHostToDevice, s));
+    }
+    HIPCHK(hipEventRecord(c->ev[1], s));
+    HIPCHK(hipMemcpyAsync(c->d_centre, centre.data(), sizeof(int32_t) * 2 * nframes * nseeds, hipMemcpyHostToDevice,
+                          s));
+    HIPCHK(hipMemcpyAsync(c->d_frames, c->h_frames.data(), sizeof(FrameState) * nframes, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(c->d_wave_total, 0, sizeof(int32_t) * (c->nodes + 130), s));
+    launch_seed_search(R, c->d_frames, nframes, nseeds, c->prm.seed_radius, c->d_centre, c->d_zbuf, s);
+    launch_seed_pick(R, c->d_frames, nframes, nseeds, c->prm.seed_radius, c->d_centre, c->d_zbuf, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(c->ev[2], s));
+
+    IterParams ip;
+    ip.max_iter = c->prm.max_iter;
+    ip.tol2 = c->prm.tol * c->prm.tol;
+    ip.zncc_min = static_cast<float>(c->prm.zncc_min);
+    ip.guess_copy = c->prm.guess_mode;
+    ip.seed_radius = c->prm.seed_radius;
+    ip.wave_total = c->d_wave_total;
+    const int grid = wave_grid_hint(c->np, c->tps, c->device);
+    const bool f64 = c->prm.reduce_fp64 != 0;
+    int k = 0, chunk = 4, waves = 0;
+    for (;;) {
+        for (int j = 0; j < chunk && k <= c->nodes; ++j, ++k)
+            if (!launch_wave(R, c->d_frames, nframes, k, c->np, c->tps, half, f64, ip, grid, s))
+                FAIL(DIC_E_UNSUPPORTED, "no kernel for shape %d, %d threads, subset %d", c->np, c->tps,
+                     c->prm.subset_size);
+        HIPCHK(hipGetLastError());
+        // wave_total[k] counts the nodes pushed into wave k (k >= 1)
+        HIPCHK(hipMemcpyAsync(c->h_pinned, c->d_wave_total + k, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (c->h_pinned[0] == 0 || k > c->nodes) break;
+        chunk = std::min(chunk * 2, 64);
+    }
+    HIPCHK(hipEventRecord(c->ev[3], s));
+    for (int f = 0; f < nframes; ++f)
+        launch_finalize(R, c->h_frames[f], c->np, c->prm.nan_unconverged != 0, s);
+    HIPCHK(hipGetLastError());
+
+    // counters: number of waves = first empty wave index
+    std::vector<int32_t> wt(k + 1);
+    HIPCHK(hipMemcpyAsync(wt.data(), c->d_wave_total, sizeof(int32_t) * (k + 1), hipMemcpyDeviceToHost, s));
+    std::vector<unsigned long long> stat(4 * nframes);
+    for (int f = 0; f < nframes; ++f)
+        HIPCHK(hipMemcpyAsync(stat.data() + 4 * f, c->frames[f].stat, sizeof(unsigned long long) * 4,
+                              hipMemcpyDeviceToHost, s));
+    double sp[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(sp, c->frames[nframes - 1].seed_p, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    waves = 1;
+    while (waves <= k && wt[waves] > 0) ++waves;
+    dic_stats S{};
+    S.nodes = c->nodes;
+    S.active = c->active;
+    S.threads_per_subset = c->tps;
+    S.frames = nframes;
+    S.waves = waves;
+    for (int f = 0; f < nframes; ++f) {
+        S.computed += static_cast<int64_t>(stat[4 * f + 0]);
+        S.converged += static_cast<int64_t>(stat[4 * f + 1]);
+        S.iterations += static_cast<int64_t>(stat[4 * f + 2]);
+    }
+    S.seed_du = static_cast<int32_t>(sp[0]);
+    S.seed_dv = static_cast<int32_t>(sp[1]);
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev[0], c->ev[3]));
+    S.ms_total = ms;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev[2], c->ev[3]));
+    S.ms_icgn = ms;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+    S.ms_prefilter = ms;
+    c->stats = S;
+    return DIC_OK;
+}
+
+dic_status dic_correlate(dic_ctx *c, const dic_image *def, const dic_seed *seeds, int32_t nseeds, dic_result *out)
+{
+    return dic_correlate_batch(c, def, 1, seeds, nseeds, out);
+}
+
+} // extern "C"

@@ -1,0 +1,102 @@
+// Internal interface between the host engine (dic_engine.hip) and the
+// gfx950 kernels (dic_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace dicmi {
+
+// Coefficient arrays carry this many mirrored samples on every side, so that
+// the 4x4 taps of any in-image point (x0-1 .. x0+2) never need index folding.
+constexpr int kPad = 4;
+// Frames one batched launch may carry.
+constexpr int kMaxFrames = 64;
+
+enum NodeStatus : int8_t {
+    kConverged = 0,
+    kNotReached = 1,
+    kNotInRoi = 2,
+    kMaxIter = 3,
+    kLowZncc = 4,
+    kOutOfBounds = 5,
+    kFlatRef = 6,
+    kFlatDef = 7,
+    kSingular = 8,
+    kNan = 9
+};
+
+// Per-node reference cache, doubles, structure of arrays [slot][node]:
+//   slot 0       f_m     subset mean of the reference intensities
+//   slot 1       df2     sum (f_i - f_m)^2 (formed exactly like the iteration's dg2)
+//   slot 2       Sfb     sum fbar_i
+//   slots 3..    SJ[np]  sum J_i          (steepest-descent images, Eq. (5) order)
+//   next np      SJf[np] sum J_i fbar_i, centred like the iteration's sums
+//   next np(np+1)/2      inverse of the Gauss-Newton Hessian, upper triangle row-major
+inline int cache_slots(int np) { return 3 + 2 * np + np * (np + 1) / 2; }
+
+struct RefView {
+    const float *coef;   // reference spline coefficients at (0,0) of a padded array
+    int64_t cpitch;      // elements per coefficient row
+    const float *pf;     // reference interpolant at every pixel [H][ppitch]
+    const float *pfx;    // its x derivative
+    const float *pfy;    // its y derivative
+    int64_t ppitch;
+    const double *cache; // [cache_slots][nodes]
+    const int8_t *flag;  // per node: -1 inactive, 0 usable, else a NodeStatus
+    const void *raw;     // resident copy of the raw reference pixels [H][W]
+    int pixel;           // dic_pixel of raw
+    int W, H, N, step, nx, ny;
+    int64_t nodes;
+};
+
+struct IterParams {
+    int max_iter;
+    double tol2;        // tol^2 (the norm is compared squared)
+    float zncc_min;
+    int guess_copy;     // 1: copy the neighbour's p, 0: extrapolate
+    int seed_radius;
+    int32_t *wave_total; // [waves] nodes pushed into each wave, summed over frames
+};
+
+// Device-resident state of one frame of a (batched) correlation.
+struct FrameState {
+    const void *dcoef;    // deformed coefficients at (0,0) of a padded array (float or __half)
+    int64_t dpitch;       // elements per row
+    const void *draw;     // raw deformed pixels
+    int64_t draw_pitch;   // bytes per row
+    int dpixel;
+    float *p;             // [np][nodes]
+    float *zncc;
+    int16_t *iters;
+    int8_t *status;
+    int32_t *wave;
+    uint64_t *pkey;       // parent key of every node (ordered ZNCC << 2 | direction priority)
+    int32_t *list0, *list1; // frontier ping-pong lists
+    int32_t *counts;      // counts[k] = size of wave k
+    double *seed_p;       // [nseeds][2]
+    int32_t *seed_nodes;  // [nseeds]
+    int32_t nseeds;
+    unsigned long long *stat; // [0] computed, [1] converged, [2] iterations
+};
+
+// ---- launchers (dic_kernels.hip) -------------------------------------
+void launch_prefilter(const void *src, int64_t src_pitch_bytes, int pixel, int W, int H, float *tmp,
+                      int64_t tmp_pitch, void *dst_at_origin, int64_t dst_pitch, bool half, hipStream_t s);
+void launch_ref_pixels(const RefView &R, float *pf, float *pfx, float *pfy, hipStream_t s);
+void launch_active(const uint8_t *roi, const RefView &R, int8_t *flag, hipStream_t s);
+void launch_ref_nodes(const RefView &R, int np, int tps, double *cache, int8_t *flag, hipStream_t s);
+void launch_init_frame(const RefView &R, const FrameState &F, int np, hipStream_t s);
+void launch_seed_search(const RefView &R, const FrameState *F_dev, int nframes, int nseeds, int radius,
+                        const int32_t *seed_center_dev, double *zbuf, hipStream_t s);
+void launch_seed_pick(const RefView &R, const FrameState *F_dev, int nframes, int nseeds, int radius,
+                      const int32_t *seed_center_dev, const double *zbuf, hipStream_t s);
+bool launch_wave(const RefView &R, const FrameState *F_dev, int nframes, int k, int np, int tps, bool half,
+                 bool f64, const IterParams &ip, int grid, hipStream_t s);
+void launch_finalize(const RefView &R, const FrameState &F, int np, bool nan_unconverged, hipStream_t s);
+int wave_grid_hint(int np, int tps, int device);
+bool supported_tps(int N, int tps);
+int tile_side(int N);
+
+} // namespace dicmi

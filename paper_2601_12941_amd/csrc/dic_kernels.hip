@@ -1,0 +1,1150 @@
+// gfx950 kernels of the reliability-guided 2D DIC path.
+//
+// Paper: Hirst et al., "Pyvale", arXiv 2601.12941.  Sec. 2.2 fixes the cubic
+// B-spline interpolation, the ZNSSD cost (Eq. (4)) and the shape functions
+// (Eq. (5)); Sec. 2.4 the reliability-guided propagation.  The per-subset
+// optimiser is inverse-compositional Gauss-Newton (the paper's LM with zero
+// damping).
+//
+// Layout: coefficient arrays are row-major with kPad mirrored samples on
+// every side; `coef` pointers address sample (0,0).  One workgroup of T
+// threads owns one subset at a time; thread t holds pixels t, t+T, t+2T, ...
+// of the subset in row-major order, their reference value and gradient in
+// registers.  The deformed coefficients around the warped subset are staged
+// in LDS and re-staged only when the warp drifts out of the staged window.
+#include "dic_internal.h"
+
+#include <climits>
+#include <float.h>
+#include <math.h>
+#include <type_traits>
+
+// Every multiply-add that should fuse is written as fmaf(); nothing else is
+// contracted, so identical expressions give identical bits in every kernel.
+#pragma clang fp contract(off)
+
+namespace dicmi {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float load_pixel(const void *base, int64_t pitch_bytes, int pixel, int x, int y)
+{
+    const char *row = static_cast<const char *>(base) + static_cast<int64_t>(y) * pitch_bytes;
+    if (pixel == 0) return static_cast<float>(reinterpret_cast<const uint8_t *>(row)[x]);
+    if (pixel == 1) return static_cast<float>(reinterpret_cast<const uint16_t *>(row)[x]);
+    return reinterpret_cast<const float *>(row)[x];
+}
+
+// whole-sample mirror fold of k onto [0, n)
+__device__ __forceinline__ int fold(int k, int n)
+{
+    if (n == 1) return 0;
+    const int P = 2 * n - 2;
+    k %= P;
+    if (k < 0) k += P;
+    return k < n ? k : P - k;
+}
+
+// Cubic B-spline weights of taps x0-1 .. x0+2 at fraction t (beta3 sampled at
+// t+1, t, t-1, t-2).
+__device__ __forceinline__ void bspline_w(float t, float &w0, float &w1, float &w2, float &w3)
+{
+    const float s = 1.0f - t;
+    const float t2 = t * t;
+    const float t3 = t2 * t;
+    w0 = s * s * s * (1.0f / 6.0f);
+    w1 = fmaf(0.5f, t3, fmaf(-1.0f, t2, 2.0f / 3.0f));
+    w2 = fmaf(-0.5f, t3, fmaf(0.5f, t2, fmaf(0.5f, t, 1.0f / 6.0f)));
+    w3 = t3 * (1.0f / 6.0f);
+}
+
+// their derivatives with respect to t
+__device__ __forceinline__ void bspline_dw(float t, float &d0, float &d1, float &d2, float &d3)
+{
+    const float s = 1.0f - t;
+    const float t2 = t * t;
+    d0 = -0.5f * (s * s);
+    d1 = fmaf(1.5f, t2, -2.0f * t);
+    d2 = fmaf(-1.5f, t2, t + 0.5f);
+    d3 = 0.5f * t2;
+}
+
+__device__ __forceinline__ float to_f32(float v) { return v; }
+__device__ __forceinline__ float to_f32(__half v) { return __half2float(v); }
+
+// 4x4 tensor-product interpolation; b points at tap (x0-1, y0-1).
+template <typename Ptr>
+__device__ __forceinline__ float interp16(Ptr b, int64_t pitch, float x0, float x1, float x2, float x3, float y0,
+                                          float y1, float y2, float y3)
+{
+    const float r0 = fmaf(x3, to_f32(b[3]), fmaf(x2, to_f32(b[2]), fmaf(x1, to_f32(b[1]), x0 * to_f32(b[0]))));
+    b += pitch;
+    const float r1 = fmaf(x3, to_f32(b[3]), fmaf(x2, to_f32(b[2]), fmaf(x1, to_f32(b[1]), x0 * to_f32(b[0]))));
+    b += pitch;
+    const float r2 = fmaf(x3, to_f32(b[3]), fmaf(x2, to_f32(b[2]), fmaf(x1, to_f32(b[1]), x0 * to_f32(b[0]))));
+    b += pitch;
+    const float r3 = fmaf(x3, to_f32(b[3]), fmaf(x2, to_f32(b[2]), fmaf(x1, to_f32(b[1]), x0 * to_f32(b[0]))));
+    return fmaf(y3, r3, fmaf(y2, r2, fmaf(y1, r1, y0 * r0)));
+}
+
+// Map a ZNCC to an unsigned key whose integer order is the float order.
+__device__ __forceinline__ uint32_t ordered_bits(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// All-reduce of NV values over the T threads of a workgroup.  Within a
+// wavefront an xor butterfly leaves every lane with bitwise the same total;
+// wavefront totals are then summed in a fixed order from LDS (double buffered
+// by `parity`, since one barrier separates consecutive uses).
+template <int T, int NV, typename V>
+__device__ __forceinline__ void block_allreduce(V (&v)[NV], V *red, int &parity)
+{
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] += __shfl_xor(v[i], m);
+    }
+    if constexpr (T > 64) {
+        constexpr int NW = T / 64;
+        V *buf = red + parity * NW * NV;
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) buf[w * NV + i] = v[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            V acc = buf[i];
+#pragma unroll
+            for (int ww = 1; ww < NW; ++ww) acc += buf[ww * NV + i];
+            v[i] = acc;
+        }
+        parity ^= 1;
+    }
+}
+
+// Per-thread partial sums of one pass over the subset, all in FP32:
+//   s[0] = sum g',  s[1] = sum g'^2,  s[2] = sum fbar g',
+//   s[3+k] = sum J_k g'  with J = grad f . dW/dp in Eq. (5) order:
+//   [fx, fy, fx dx, fx dy, fy dx, fy dy, fx dx^2, fx dx dy, fx dy^2, fy dx^2, fy dx dy, fy dy^2].
+// g' is the deformed value minus the reference subset mean.
+template <int NP>
+__device__ __forceinline__ void accumulate(float (&s)[3 + NP], float g, float fb, float gx, float gy, float dx,
+                                           float dy)
+{
+    s[0] = s[0] + g;
+    s[1] = fmaf(g, g, s[1]);
+    s[2] = fmaf(fb, g, s[2]);
+    const float a = gx * g;
+    const float c = gy * g;
+    s[3] = s[3] + a;
+    s[4] = s[4] + c;
+    s[5] = fmaf(a, dx, s[5]);
+    s[6] = fmaf(a, dy, s[6]);
+    s[7] = fmaf(c, dx, s[7]);
+    s[8] = fmaf(c, dy, s[8]);
+    if constexpr (NP == 12) {
+        const float ax = a * dx, ay = a * dy, cx = c * dx, cy = c * dy;
+        s[9] = fmaf(ax, dx, s[9]);
+        s[10] = fmaf(ax, dy, s[10]);
+        s[11] = fmaf(ay, dy, s[11]);
+        s[12] = fmaf(cx, dx, s[12]);
+        s[13] = fmaf(cx, dy, s[13]);
+        s[14] = fmaf(cy, dy, s[14]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// B-spline prefilter.  The exact inverse of the sampled cubic B-spline
+// (c[k-1] + 4c[k] + c[k+1])/6 = s[k] has the two-sided impulse response
+// h[n] = sqrt(3) (sqrt(3)-2)^|n| (Unser 1993); truncated at |n| <= 15 its
+// tail is below 3.4e-9 of max|s|, far under FP32 resolution.  With the
+// mirror-extended input the truncated FIR reproduces the mirror-boundary
+// solution.  Separable: rows into an FP32 scratch array, then columns into the
+// padded coefficient array (padding filled with the mirrored coefficients).
+// ---------------------------------------------------------------------------
+constexpr int kFir = 15;
+__constant__ float c_fir[2 * kFir + 1];
+
+constexpr int kRowBlock = 256;
+
+__global__ __launch_bounds__(kRowBlock) void k_prefilter_rows(const void *src, int64_t sp, int pixel, int W,
+                                                               float *tmp, int64_t tp)
+{
+    __shared__ float s[kRowBlock + 2 * kFir];
+    const int y = blockIdx.y;
+    const int xb = blockIdx.x * kRowBlock;
+    for (int i = threadIdx.x; i < kRowBlock + 2 * kFir; i += kRowBlock) {
+        const int x = xb - kFir + i;
+        s[i] = load_pixel(src, sp, pixel, fold(x, W), y);
+    }
+    __syncthreads();
+    const int x = xb + threadIdx.x;
+    if (x < W) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int n = -kFir; n <= kFir; ++n) acc = fmaf(c_fir[n + kFir], s[threadIdx.x + kFir - n], acc);
+        tmp[static_cast<int64_t>(y) * tp + x] = acc;
+    }
+}
+
+__device__ __forceinline__ void store_coef(float *d, float v) { *d = v; }
+__device__ __forceinline__ void store_coef(__half *d, float v) { *d = __float2half(v); }
+
+template <typename OutT>
+__global__ __launch_bounds__(256) void k_prefilter_cols(const float *tmp, int64_t tp, int W, int H, OutT *dst,
+                                                         int64_t dp)
+{
+    const int x = blockIdx.x * 64 + threadIdx.x - kPad;
+    const int y = blockIdx.y * 4 + threadIdx.y - kPad;
+    if (x >= W + kPad || y >= H + kPad) return;
+    const int xm = fold(x, W);
+    const int ym = fold(y, H);
+    float acc = 0.0f;
+#pragma unroll
+    for (int n = -kFir; n <= kFir; ++n)
+        acc = fmaf(c_fir[n + kFir], tmp[static_cast<int64_t>(fold(ym - n, H)) * tp + xm], acc);
+    store_coef(dst + static_cast<int64_t>(y) * dp + x, acc);
+}
+
+void launch_prefilter(const void *src, int64_t src_pitch_bytes, int pixel, int W, int H, float *tmp,
+                      int64_t tmp_pitch, void *dst, int64_t dst_pitch, bool half, hipStream_t s)
+{
+    static bool taps_ready[64] = {};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (dev < 0 || dev >= 64 || !taps_ready[dev]) {
+        float h[2 * kFir + 1];
+        const double z = sqrt(3.0) - 2.0;
+        for (int n = -kFir; n <= kFir; ++n) h[n + kFir] = static_cast<float>(sqrt(3.0) * pow(fabs(z), abs(n)) *
+                                                                             ((abs(n) & 1) ? -1.0 : 1.0));
+        (void)hipMemcpyToSymbol(HIP_SYMBOL(c_fir), h, sizeof(h));
+        if (dev >= 0 && dev < 64) taps_ready[dev] = true;
+    }
+    dim3 g1((W + kRowBlock - 1) / kRowBlock, H);
+    k_prefilter_rows<<<g1, kRowBlock, 0, s>>>(src, src_pitch_bytes, pixel, W, tmp, tmp_pitch);
+    dim3 g2((W + 2 * kPad + 63) / 64, (H + 2 * kPad + 3) / 4);
+    if (half)
+        k_prefilter_cols<__half><<<g2, dim3(64, 4), 0, s>>>(tmp, tmp_pitch, W, H, static_cast<__half *>(dst),
+                                                             dst_pitch);
+    else
+        k_prefilter_cols<float><<<g2, dim3(64, 4), 0, s>>>(tmp, tmp_pitch, W, H, static_cast<float *>(dst),
+                                                            dst_pitch);
+}
+
+// ---------------------------------------------------------------------------
+// Reference precompute: the interpolant and its gradient at every pixel
+// (t = 0 weights, the same expression the iteration uses for the deformed
+// image), then per node the sums the iteration reuses and the inverse of the
+// Gauss-Newton Hessian.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_ref_pixels(RefView R, float *pf, float *pfx, float *pfy)
+{
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    if (x >= R.W || y >= R.H) return;
+    float w0, w1, w2, w3, d0, d1, d2, d3;
+    bspline_w(0.0f, w0, w1, w2, w3);
+    bspline_dw(0.0f, d0, d1, d2, d3);
+    const float *b = R.coef + static_cast<int64_t>(y - 1) * R.cpitch + (x - 1);
+    const int64_t o = static_cast<int64_t>(y) * R.ppitch + x;
+    pf[o] = interp16(b, R.cpitch, w0, w1, w2, w3, w0, w1, w2, w3);
+    pfx[o] = interp16(b, R.cpitch, d0, d1, d2, d3, w0, w1, w2, w3);
+    pfy[o] = interp16(b, R.cpitch, w0, w1, w2, w3, d0, d1, d2, d3);
+}
+
+void launch_ref_pixels(const RefView &R, float *pf, float *pfx, float *pfy, hipStream_t s)
+{
+    dim3 g((R.W + 63) / 64, (R.H + 3) / 4);
+    k_ref_pixels<<<g, dim3(64, 4), 0, s>>>(R, pf, pfx, pfy);
+}
+
+// A node is active iff all N^2 pixels of its subset are inside the ROI.
+__global__ void k_active(const uint8_t *roi, RefView R, int8_t *flag)
+{
+    const int64_t node = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (node >= R.nodes) return;
+    const int ix = static_cast<int>(node % R.nx), iy = static_cast<int>(node / R.nx);
+    const int x0 = ix * R.step, y0 = iy * R.step;
+    bool ok = true;
+    if (roi) {
+        for (int y = 0; y < R.N && ok; ++y) {
+            const uint8_t *row = roi + static_cast<int64_t>(y0 + y) * R.W + x0;
+            for (int x = 0; x < R.N; ++x) ok = ok && row[x] != 0;
+        }
+    }
+    flag[node] = ok ? 0 : -1;
+}
+
+void launch_active(const uint8_t *roi, const RefView &R, int8_t *flag, hipStream_t s)
+{
+    const int64_t blocks = (R.nodes + 255) / 256;
+    k_active<<<static_cast<unsigned>(blocks), 256, 0, s>>>(roi, R, flag);
+}
+
+template <int NP>
+__device__ __forceinline__ void steepest(double (&J)[NP], double gx, double gy, double dx, double dy)
+{
+    J[0] = gx;
+    J[1] = gy;
+    J[2] = gx * dx;
+    J[3] = gx * dy;
+    J[4] = gy * dx;
+    J[5] = gy * dy;
+    if constexpr (NP == 12) {
+        J[6] = gx * dx * dx;
+        J[7] = gx * dx * dy;
+        J[8] = gx * dy * dy;
+        J[9] = gy * dx * dx;
+        J[10] = gy * dx * dy;
+        J[11] = gy * dy * dy;
+    }
+}
+
+// Degenerate-case thresholds: a subset is flat when its RMS deviation is below
+// 1e-6 of its mean level; a Cholesky pivot is singular below 1e-10 of the
+// largest Hessian diagonal, each entry taken in the units of the convergence
+// norm (weights 1, h^2, h^4 for translation, gradient and curvature terms).
+constexpr double kFlatRel = 1e-6;
+constexpr double kSingularRel = 1e-10;
+
+template <int NP, int T, int P>
+__global__ __launch_bounds__(T) void k_ref_nodes(RefView R, double *cache, int8_t *flag)
+{
+    constexpr int NH = NP * (NP + 1) / 2;
+    constexpr int NV = 3 + NP + NP + NH;
+    __shared__ double red[2 * (T / 64) * NV];
+    int parity = 0;
+    const int N = R.N, h = (N - 1) / 2, n = N * N;
+    const int t = threadIdx.x;
+    float dxs[P], dys[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        const int i = t + T * j;
+        dxs[j] = static_cast<float>(i % N - h);
+        dys[j] = static_cast<float>(i / N - h);
+    }
+    for (int64_t node = blockIdx.x; node < R.nodes; node += gridDim.x) {
+        if (flag[node] < 0) continue;
+        const int xc = h + static_cast<int>(node % R.nx) * R.step;
+        const int yc = h + static_cast<int>(node / R.nx) * R.step;
+        float fv[P], gxv[P], gyv[P];
+        double sf[1] = {0.0};
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            fv[j] = gxv[j] = gyv[j] = 0.0f;
+            if (t + T * j < n) {
+                const int64_t o = static_cast<int64_t>(yc + static_cast<int>(dys[j])) * R.ppitch + xc +
+                                  static_cast<int>(dxs[j]);
+                fv[j] = R.pf[o];
+                gxv[j] = R.pfx[o];
+                gyv[j] = R.pfy[o];
+                sf[0] += static_cast<double>(fv[j]);
+            }
+        }
+        block_allreduce<T, 1>(sf, red, parity);
+        const double fm = sf[0] / n;
+        const float fm32 = static_cast<float>(fm);
+        float s[3 + NP];
+#pragma unroll
+        for (int i = 0; i < 3 + NP; ++i) s[i] = 0.0f;
+        double v[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] = 0.0;
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            if (t + T * j < n) {
+                const float fb = fv[j] - fm32;
+                accumulate<NP>(s, fb, fb, gxv[j], gyv[j], dxs[j], dys[j]);
+                double J[NP];
+                steepest<NP>(J, gxv[j], gyv[j], dxs[j], dys[j]);
+                int q = 3 + NP + NP;
+#pragma unroll
+                for (int a = 0; a < NP; ++a) {
+                    v[3 + NP + a] += J[a];
+#pragma unroll
+                    for (int b = a; b < NP; ++b) {
+                        v[q] = fma(J[a], J[b], v[q]);
+                        ++q;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 3 + NP; ++i) v[i] = static_cast<double>(s[i]);
+        block_allreduce<T, NV>(v, red, parity);
+        if (t == 0) {
+            // same expressions as the iteration's dg2 and J^T gbar, so that an
+            // identical deformed subset gives a bitwise-zero increment
+            const double S0 = v[0], S1 = v[1];
+            const double gm = S0 / n;
+            const double df2 = S1 - S0 * gm;
+            double SJ[NP], SJf[NP];
+#pragma unroll
+            for (int a = 0; a < NP; ++a) {
+                SJ[a] = v[3 + NP + a];
+                SJf[a] = v[3 + a] - gm * SJ[a];
+            }
+            int8_t st = 0;
+            const double lev = fmax(1.0, fabs(fm));
+            if (isnan(df2)) st = kNan;
+            else if (df2 <= n * (kFlatRel * lev) * (kFlatRel * lev)) st = kFlatRef;
+            // centred Hessian H = sum J J^T - SJ SJ^T / n, Cholesky L L^T
+            double L[NP][NP];
+            double Hd[NP];
+            {
+                int q = 3 + NP + NP;
+#pragma unroll
+                for (int a = 0; a < NP; ++a)
+#pragma unroll
+                    for (int b = a; b < NP; ++b) {
+                        const double hv = v[q++] - SJ[a] * SJ[b] / n;
+                        L[a][b] = hv;
+                        L[b][a] = hv;
+                    }
+            }
+            double hmax = 0.0, scl[NP];
+#pragma unroll
+            for (int a = 0; a < NP; ++a) {
+                scl[a] = a < 2 ? 1.0 : (a < 6 ? static_cast<double>(h) * h : static_cast<double>(h) * h * h * h);
+                Hd[a] = L[a][a];
+                hmax = fmax(hmax, Hd[a] / scl[a]);
+            }
+            // in-place Cholesky on the lower triangle
+            for (int a = 0; a < NP && st == 0; ++a) {
+                double d = L[a][a];
+                for (int k = 0; k < a; ++k) d -= L[a][k] * L[a][k];
+                if (isnan(d)) { st = kNan; break; }
+                if (!(d > kSingularRel * scl[a] * hmax)) { st = kSingular; break; }
+                const double la = sqrt(d);
+                L[a][a] = la;
+                for (int i = a + 1; i < NP; ++i) {
+                    double x = L[i][a];
+                    for (int k = 0; k < a; ++k) x -= L[i][k] * L[a][k];
+                    L[i][a] = x / la;
+                }
+            }
+            double *c = cache;
+            const int64_t nn = R.nodes;
+            c[0 * nn + node] = fm;
+            c[1 * nn + node] = df2;
+            c[2 * nn + node] = S0;
+#pragma unroll
+            for (int a = 0; a < NP; ++a) {
+                c[(3 + a) * nn + node] = SJ[a];
+                c[(3 + NP + a) * nn + node] = SJf[a];
+            }
+            if (st == 0) {
+                // H^{-1} = L^{-T} L^{-1}; Li = L^{-1} (lower), column by column
+                double Li[NP][NP];
+                for (int j = 0; j < NP; ++j) {
+                    for (int i = 0; i < NP; ++i) Li[i][j] = 0.0;
+                    Li[j][j] = 1.0 / L[j][j];
+                    for (int i = j + 1; i < NP; ++i) {
+                        double x = 0.0;
+                        for (int k = j; k < i; ++k) x -= L[i][k] * Li[k][j];
+                        Li[i][j] = x / L[i][i];
+                    }
+                }
+                int q = 3 + 2 * NP;
+                for (int a = 0; a < NP; ++a)
+                    for (int b = a; b < NP; ++b) {
+                        double x = 0.0;
+                        for (int k = b; k < NP; ++k) x += Li[k][a] * Li[k][b];
+                        c[static_cast<int64_t>(q++) * nn + node] = x;
+                    }
+            }
+            flag[node] = st;
+        }
+    }
+}
+
+template <int NP, int T, int P>
+static void ref_nodes_inst(const RefView &R, double *cache, int8_t *flag, hipStream_t s)
+{
+    const int64_t blocks = R.nodes < 8192 ? R.nodes : 8192;
+    k_ref_nodes<NP, T, P><<<static_cast<unsigned>(blocks < 1 ? 1 : blocks), T, 0, s>>>(R, cache, flag);
+}
+
+// ---------------------------------------------------------------------------
+// Seed initialisation: ZNCC of the raw reference subset against the raw
+// deformed subset at every integer shift of round(u0, v0) + [-R, R]^2 (shifts
+// leaving the image are skipped).  Integer pixels are summed exactly in int64,
+// the ZNCC formed in FP64; the best shift wins, exact ties going to the
+// smaller du^2 + dv^2, then smaller dv, then smaller du.
+// ---------------------------------------------------------------------------
+constexpr int kSeedBlock = 256;
+
+__global__ __launch_bounds__(kSeedBlock) void k_seed_search(RefView R, const FrameState *frames, int nseeds,
+                                                            int radius, const int32_t *centre, double *zbuf)
+{
+    const int side = 2 * radius + 1;
+    const int shift = blockIdx.x, si = blockIdx.y, f = blockIdx.z;
+    const FrameState &F = frames[f];
+    if (si >= F.nseeds) return;
+    const int node = F.seed_nodes[si];
+    const int du = centre[2 * (f * nseeds + si)] + shift % side - radius;
+    const int dv = centre[2 * (f * nseeds + si) + 1] + shift / side - radius;
+    const int N = R.N, h = (N - 1) / 2, n = N * N;
+    const int xc = h + (node % R.nx) * R.step, yc = h + (node / R.nx) * R.step;
+    double *out = zbuf + (static_cast<int64_t>(f) * nseeds + si) * side * side + shift;
+    if (xc - h + du < 0 || xc + h + du > R.W - 1 || yc - h + dv < 0 || yc + h + dv > R.H - 1) {
+        if (threadIdx.x == 0) *out = -INFINITY;
+        return;
+    }
+    const int64_t rpitch = static_cast<int64_t>(R.W) * (R.pixel == 0 ? 1 : (R.pixel == 1 ? 2 : 4));
+    __shared__ long long si64[kSeedBlock][5];
+    __shared__ double sd[kSeedBlock][5];
+    const bool integer = R.pixel != 2;
+    long long a[5] = {0, 0, 0, 0, 0};
+    double d[5] = {0, 0, 0, 0, 0};
+    for (int i = threadIdx.x; i < n; i += kSeedBlock) {
+        const int x = xc + i % N - h, y = yc + i / N - h;
+        const float fv = load_pixel(R.raw, rpitch, R.pixel, x, y);
+        const float gv = load_pixel(F.draw, F.draw_pitch, F.dpixel, x + du, y + dv);
+        if (integer) {
+            const long long fi = static_cast<long long>(fv), gi = static_cast<long long>(gv);
+            a[0] += fi; a[1] += fi * fi; a[2] += gi; a[3] += gi * gi; a[4] += fi * gi;
+        } else {
+            const double fd = fv, gd = gv;
+            d[0] += fd; d[1] += fd * fd; d[2] += gd; d[3] += gd * gd; d[4] += fd * gd;
+        }
+    }
+    for (int k = 0; k < 5; ++k) { si64[threadIdx.x][k] = a[k]; sd[threadIdx.x][k] = d[k]; }
+    __syncthreads();
+    for (int m = kSeedBlock / 2; m > 0; m >>= 1) {
+        if (threadIdx.x < m)
+            for (int k = 0; k < 5; ++k) {
+                si64[threadIdx.x][k] += si64[threadIdx.x + m][k];
+                sd[threadIdx.x][k] += sd[threadIdx.x + m][k];
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double num, A, B;
+        if (integer) {
+            const long long sf = si64[0][0], sff = si64[0][1], sg = si64[0][2], sgg = si64[0][3], sfg = si64[0][4];
+            num = static_cast<double>(static_cast<long long>(n) * sfg - sf * sg);
+            A = static_cast<double>(static_cast<long long>(n) * sff - sf * sf);
+            B = static_cast<double>(static_cast<long long>(n) * sgg - sg * sg);
+        } else {
+            num = n * sd[0][4] - sd[0][0] * sd[0][2];
+            A = n * sd[0][1] - sd[0][0] * sd[0][0];
+            B = n * sd[0][3] - sd[0][2] * sd[0][2];
+        }
+        *out = (A > 0.0 && B > 0.0) ? num / sqrt(A * B) : -INFINITY;
+    }
+}
+
+void launch_seed_search(const RefView &R, const FrameState *F_dev, int nframes, int nseeds, int radius,
+                        const int32_t *centre, double *zbuf, hipStream_t s)
+{
+    const int side = 2 * radius + 1;
+    dim3 g(side * side, nseeds, nframes);
+    k_seed_search<<<g, kSeedBlock, 0, s>>>(R, F_dev, nseeds, radius, centre, zbuf);
+}
+
+__global__ void k_seed_pick(RefView R, const FrameState *frames, int nseeds, int radius, const int32_t *centre,
+                            const double *zbuf)
+{
+    const int si = threadIdx.x + blockIdx.x * blockDim.x, f = blockIdx.y;
+    const FrameState &F = frames[f];
+    if (si >= F.nseeds) return;
+    const int side = 2 * radius + 1;
+    const double *z = zbuf + (static_cast<int64_t>(f) * nseeds + si) * side * side;
+    int bu = 0, bv = 0, found = 0;
+    double bz = 0.0;
+    for (int q = 0; q < side * side; ++q) {
+        if (z[q] == -INFINITY) continue;
+        const int du = centre[2 * (f * nseeds + si)] + q % side - radius;
+        const int dv = centre[2 * (f * nseeds + si) + 1] + q / side - radius;
+        bool better = !found || z[q] > bz;
+        if (found && z[q] == bz) {
+            const long d2 = static_cast<long>(du) * du + static_cast<long>(dv) * dv;
+            const long b2 = static_cast<long>(bu) * bu + static_cast<long>(bv) * bv;
+            better = d2 < b2 || (d2 == b2 && (dv < bv || (dv == bv && du < bu)));
+        }
+        if (better) { found = 1; bz = z[q]; bu = du; bv = dv; }
+    }
+    if (si == 0) F.counts[0] = F.nseeds;
+    F.seed_p[2 * si] = bu;
+    F.seed_p[2 * si + 1] = bv;
+    F.wave[F.seed_nodes[si]] = 0;
+    F.list0[si] = F.seed_nodes[si];
+}
+
+void launch_seed_pick(const RefView &R, const FrameState *F_dev, int nframes, int nseeds, int radius,
+                      const int32_t *centre, const double *zbuf, hipStream_t s)
+{
+    dim3 g((nseeds + 63) / 64, nframes);
+    k_seed_pick<<<g, 64, 0, s>>>(R, F_dev, nseeds, radius, centre, zbuf);
+}
+
+// ---------------------------------------------------------------------------
+// Per-frame initialisation and finalisation.
+// ---------------------------------------------------------------------------
+__global__ void k_init_frame(RefView R, FrameState F, int np)
+{
+    const int64_t node = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (node >= R.nodes) return;
+    for (int j = 0; j < np; ++j) F.p[j * R.nodes + node] = 0.0f;
+    F.zncc[node] = 0.0f;
+    F.iters[node] = 0;
+    F.status[node] = R.flag[node] < 0 ? kNotInRoi : kNotReached;
+    F.wave[node] = -1;
+    F.pkey[node] = 0;
+    F.counts[node] = 0;
+    if (node == 0) {
+        F.counts[R.nodes] = 0;
+        F.counts[R.nodes + 1] = 0;
+    }
+}
+
+void launch_init_frame(const RefView &R, const FrameState &F, int np, hipStream_t s)
+{
+    k_init_frame<<<static_cast<unsigned>((R.nodes + 255) / 256), 256, 0, s>>>(R, F, np);
+}
+
+__global__ void k_finalize(RefView R, FrameState F, int np)
+{
+    const int64_t node = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (node >= R.nodes) return;
+    if (F.status[node] != kConverged)
+        for (int j = 0; j < np; ++j) F.p[j * R.nodes + node] = __int_as_float(0x7fc00000);
+}
+
+void launch_finalize(const RefView &R, const FrameState &F, int np, bool nan_unconverged, hipStream_t s)
+{
+    if (!nan_unconverged) return;
+    k_finalize<<<static_cast<unsigned>((R.nodes + 255) / 256), 256, 0, s>>>(R, F, np);
+}
+
+// ---------------------------------------------------------------------------
+// Inverse-compositional update p <- p o dp^{-1} (FP64).
+// ---------------------------------------------------------------------------
+// Affine: with M(q) = [[1+q2, q3, q0], [q4, 1+q5, q1], [0, 0, 1]], the product
+// M(p) M(dp)^{-1} written so that every entry is formed from differences
+// p_j - dp_j (no "(1 + small) - 1" cancellation; exact when dp = 0).
+__device__ __forceinline__ void compose_affine(double (&p)[6], const double (&d)[6])
+{
+    const double a = 1.0 + d[2], b = d[3], c = d[4], e = 1.0 + d[5];
+    const double det = a * e - b * c;
+    const double r = 1.0 / det;
+    // translation part of M(dp)^{-1}: -(M2^{-1}) (d0, d1)
+    const double tx = (b * d[1] - e * d[0]) * r;
+    const double ty = (c * d[0] - a * d[1]) * r;
+    const double n2 = (e * (p[2] - d[2]) - c * (p[3] - d[3])) * r;
+    const double n3 = ((p[3] - d[3]) + p[3] * d[2] - p[2] * d[3]) * r;
+    const double n4 = ((p[4] - d[4]) + p[4] * d[5] - p[5] * d[4]) * r;
+    const double n5 = (a * (p[5] - d[5]) - b * (p[4] - d[4])) * r;
+    const double n0 = p[0] + (1.0 + p[2]) * tx + p[3] * ty;
+    const double n1 = p[1] + p[4] * tx + (1.0 + p[5]) * ty;
+    p[0] = n0; p[1] = n1; p[2] = n2; p[3] = n3; p[4] = n4; p[5] = n5;
+}
+
+// Quadratic: lift q to the 6x6 matrix Q(q) acting on the monomials
+// [dx^2, dx dy, dy^2, dx, dy, 1] (each image monomial truncated at second
+// order); the update keeps the X and Y rows of Q(p) Q(dp)^{-1}, found by
+// solving Q(dp)^T r = (row of Q(p))^T with partial pivoting.
+__device__ __forceinline__ void lift(const double (&q)[12], double (&Q)[6][6])
+{
+    const double U = q[0], V = q[1], A = 1.0 + q[2], B = q[3], C = q[4], D = 1.0 + q[5];
+    const double a0 = q[6], a1 = q[7], a2 = q[8], b0 = q[9], b1 = q[10], b2 = q[11];
+    // X^2
+    Q[0][0] = A * A + 2.0 * U * a0; Q[0][1] = 2.0 * (A * B + U * a1); Q[0][2] = B * B + 2.0 * U * a2;
+    Q[0][3] = 2.0 * U * A; Q[0][4] = 2.0 * U * B; Q[0][5] = U * U;
+    // X Y
+    Q[1][0] = A * C + U * b0 + V * a0; Q[1][1] = A * D + B * C + U * b1 + V * a1; Q[1][2] = B * D + U * b2 + V * a2;
+    Q[1][3] = U * C + V * A; Q[1][4] = U * D + V * B; Q[1][5] = U * V;
+    // Y^2
+    Q[2][0] = C * C + 2.0 * V * b0; Q[2][1] = 2.0 * (C * D + V * b1); Q[2][2] = D * D + 2.0 * V * b2;
+    Q[2][3] = 2.0 * V * C; Q[2][4] = 2.0 * V * D; Q[2][5] = V * V;
+    // X, Y, 1
+    Q[3][0] = a0; Q[3][1] = a1; Q[3][2] = a2; Q[3][3] = A; Q[3][4] = B; Q[3][5] = U;
+    Q[4][0] = b0; Q[4][1] = b1; Q[4][2] = b2; Q[4][3] = C; Q[4][4] = D; Q[4][5] = V;
+    Q[5][0] = 0.0; Q[5][1] = 0.0; Q[5][2] = 0.0; Q[5][3] = 0.0; Q[5][4] = 0.0; Q[5][5] = 1.0;
+}
+
+__device__ __forceinline__ void compose_quadratic(double (&p)[12], const double (&d)[12])
+{
+    double Qp[6][6], M[6][8];
+    lift(p, Qp);
+    {
+        double Qd[6][6];
+        lift(d, Qd);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+#pragma unroll
+            for (int j = 0; j < 6; ++j) M[i][j] = Qd[j][i];   // transpose
+            M[i][6] = Qp[3][i];
+            M[i][7] = Qp[4][i];
+        }
+    }
+#pragma unroll
+    for (int col = 0; col < 6; ++col) {
+        int piv = col;
+        double best = fabs(M[col][col]);
+#pragma unroll
+        for (int r = col + 1; r < 6; ++r)
+            if (fabs(M[r][col]) > best) { best = fabs(M[r][col]); piv = r; }
+        if (piv != col) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) { const double tv = M[col][k]; M[col][k] = M[piv][k]; M[piv][k] = tv; }
+        }
+        const double inv = 1.0 / M[col][col];
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+            if (r == col) continue;
+            const double fct = M[r][col] * inv;
+#pragma unroll
+            for (int k = col; k < 8; ++k) M[r][k] -= fct * M[col][k];
+        }
+    }
+    double x[6], y[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        x[i] = M[i][6] / M[i][i];
+        y[i] = M[i][7] / M[i][i];
+    }
+    p[0] = x[5]; p[1] = y[5];
+    p[2] = x[3] - 1.0; p[3] = x[4];
+    p[4] = y[3]; p[5] = y[4] - 1.0;
+    p[6] = x[0]; p[7] = x[1]; p[8] = x[2];
+    p[9] = y[0]; p[10] = y[1]; p[11] = y[2];
+}
+
+// ---------------------------------------------------------------------------
+// One frontier wave: every subset of wave k of every frame.
+// ---------------------------------------------------------------------------
+template <int NP, int T, int P, bool F64>
+__global__ __launch_bounds__(T) void k_wave(RefView R, const FrameState *__restrict__ frames, int nframes, int k,
+                                            IterParams ip, int ts, int half)
+{
+    using Acc = typename std::conditional<F64, double, float>::type;
+    constexpr int NS = 3 + NP;
+    constexpr int NH = NP * (NP + 1) / 2;
+    extern __shared__ float tile[];  // ts * ts deformed coefficients
+    __shared__ Acc red[2 * (T / 64) * NS];
+    __shared__ int prefix[kMaxFrames + 1];
+
+    const int t = threadIdx.x;
+    if (t == 0) {
+        int acc = 0;
+        for (int f = 0; f < nframes; ++f) {
+            prefix[f] = acc;
+            acc += frames[f].counts[k];
+        }
+        prefix[nframes] = acc;
+    }
+    __syncthreads();
+    const int total = __builtin_amdgcn_readfirstlane(prefix[nframes]);
+    if (static_cast<int>(blockIdx.x) >= total) return;
+
+    const int N = R.N, h = (N - 1) / 2, n = N * N;
+    const int64_t nn = R.nodes;
+    float dxs[P], dys[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        const int i = t + T * j;
+        dxs[j] = static_cast<float>(i % N - h);
+        dys[j] = static_cast<float>(i / N - h);
+    }
+    int parity = 0;
+    unsigned long long cnt_computed = 0, cnt_converged = 0, cnt_iters = 0;
+    int cur_frame = -1;
+
+    for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
+        int f = 0;
+        while (f + 1 < nframes && prefix[f + 1] <= gi) ++f;
+        f = __builtin_amdgcn_readfirstlane(f);
+        if (f != cur_frame && cur_frame >= 0 && t == 0) {
+            unsigned long long *st = frames[cur_frame].stat;
+            atomicAdd(st + 0, cnt_computed);
+            atomicAdd(st + 1, cnt_converged);
+            atomicAdd(st + 2, cnt_iters);
+            cnt_computed = cnt_converged = cnt_iters = 0;
+        }
+        cur_frame = f;
+        const FrameState &F = frames[f];
+        const int li = __builtin_amdgcn_readfirstlane(gi - prefix[f]);
+        const int32_t *lin = (k & 1) ? F.list1 : F.list0;
+        int32_t *lout = (k & 1) ? F.list0 : F.list1;
+        const int node = __builtin_amdgcn_readfirstlane(lin[li]);
+        const int ix = node % R.nx, iy = node / R.nx;
+        const int xc = h + ix * R.step, yc = h + iy * R.step;
+
+        // ---- initial guess
+        double p[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) p[j] = 0.0;
+        if (k == 0) {
+            p[0] = F.seed_p[2 * li];
+            p[1] = F.seed_p[2 * li + 1];
+        } else {
+            const uint32_t dir = static_cast<uint32_t>(F.pkey[node] & 3u);
+            // priority 3: parent on the left, 2: right, 1: above, 0: below
+            // (clamped: a listed node always has a key, the clamp only guards the read)
+            const int px = min(max(ix + (dir == 3 ? -1 : (dir == 2 ? 1 : 0)), 0), R.nx - 1);
+            const int py = min(max(iy + (dir == 1 ? -1 : (dir == 0 ? 1 : 0)), 0), R.ny - 1);
+            const int64_t par = static_cast<int64_t>(py) * R.nx + px;
+            double q[NP];
+#pragma unroll
+            for (int j = 0; j < NP; ++j) q[j] = static_cast<double>(F.p[j * nn + par]);
+#pragma unroll
+            for (int j = 0; j < NP; ++j) p[j] = q[j];
+            if (!ip.guess_copy) {
+                const double ex = static_cast<double>((ix - px) * R.step);
+                const double ey = static_cast<double>((iy - py) * R.step);
+                p[0] = q[0] + q[2] * ex + q[3] * ey;
+                p[1] = q[1] + q[4] * ex + q[5] * ey;
+                if constexpr (NP == 12) {
+                    p[0] += q[6] * ex * ex + q[7] * ex * ey + q[8] * ey * ey;
+                    p[1] += q[9] * ex * ex + q[10] * ex * ey + q[11] * ey * ey;
+                    p[2] = q[2] + 2.0 * q[6] * ex + q[7] * ey;
+                    p[3] = q[3] + q[7] * ex + 2.0 * q[8] * ey;
+                    p[4] = q[4] + 2.0 * q[9] * ex + q[10] * ey;
+                    p[5] = q[5] + q[10] * ex + 2.0 * q[11] * ey;
+                }
+            }
+        }
+
+        int status = kMaxIter;
+        int iters = 0;
+        float zncc_out = 0.0f;
+        const int8_t rf = R.flag[node];
+        if (rf != 0) {
+            status = rf;
+        } else {
+            // ---- reference cache and per-pixel reference data
+            const double fm = R.cache[node];
+            const double df2 = R.cache[nn + node];
+            const double Sfb = R.cache[2 * nn + node];
+            double SJ[NP], SJf[NP], Hi[NH];
+#pragma unroll
+            for (int a = 0; a < NP; ++a) {
+                SJ[a] = R.cache[(3 + a) * nn + node];
+                SJf[a] = R.cache[(3 + NP + a) * nn + node];
+            }
+#pragma unroll
+            for (int q = 0; q < NH; ++q) Hi[q] = R.cache[(3 + 2 * NP + q) * nn + node];
+            const float fm32 = static_cast<float>(fm);
+            float fb[P], gx[P], gy[P];
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+                fb[j] = gx[j] = gy[j] = 0.0f;
+                if (t + T * j < n) {
+                    const int64_t o = static_cast<int64_t>(yc + static_cast<int>(dys[j])) * R.ppitch + xc +
+                                      static_cast<int>(dxs[j]);
+                    fb[j] = R.pf[o] - fm32;
+                    gx[j] = R.pfx[o];
+                    gy[j] = R.pfy[o];
+                }
+            }
+            const double hd = static_cast<double>(h);
+            int tox = INT_MIN / 2, toy = INT_MIN / 2;   // staged window origin (global sample coords)
+
+            for (int it = 1; it <= ip.max_iter; ++it) {
+                iters = it;
+                // ---- bounding box of the warped subset (exact for affine: its corners)
+                double xmin, xmax, ymin, ymax;
+                {
+                    const double ux = (1.0 + p[2]) * hd, uy = p[3] * hd;
+                    const double vx = p[4] * hd, vy = (1.0 + p[5]) * hd;
+                    const double cx = xc + p[0], cy = yc + p[1];
+                    const double rx = fabs(ux) + fabs(uy), ry = fabs(vx) + fabs(vy);
+                    xmin = cx - rx; xmax = cx + rx; ymin = cy - ry; ymax = cy + ry;
+                    if constexpr (NP == 12) {
+                        const double qx = (fabs(p[6]) + fabs(p[7]) + fabs(p[8])) * hd * hd;
+                        const double qy = (fabs(p[9]) + fabs(p[10]) + fabs(p[11])) * hd * hd;
+                        xmin -= qx; xmax += qx; ymin -= qy; ymax += qy;
+                    }
+                }
+                if (isnan(xmin + xmax + ymin + ymax)) { status = kNan; break; }
+                if (!(xmin >= 0.0 && xmax <= R.W - 1.0 && ymin >= 0.0 && ymax <= R.H - 1.0)) {
+                    bool oob = true;
+                    if constexpr (NP == 12) {
+                        // the box is conservative for the quadratic shape: check every point
+                        int any = 0;
+#pragma unroll
+                        for (int j = 0; j < P; ++j) {
+                            if (t + T * j < n) {
+                                const double dx = dxs[j], dy = dys[j];
+                                const double X = xc + dx + p[0] + p[2] * dx + p[3] * dy + p[6] * dx * dx +
+                                                 p[7] * dx * dy + p[8] * dy * dy;
+                                const double Y = yc + dy + p[1] + p[4] * dx + p[5] * dy + p[9] * dx * dx +
+                                                 p[10] * dx * dy + p[11] * dy * dy;
+                                any |= !(X >= 0.0 && X <= R.W - 1.0 && Y >= 0.0 && Y <= R.H - 1.0);
+                            }
+                        }
+                        oob = __syncthreads_or(any) != 0;
+                        // the exact extent is still within the image: use a box clipped to it
+                        xmin = fmax(xmin, 0.0); ymin = fmax(ymin, 0.0);
+                        xmax = fmin(xmax, R.W - 1.0); ymax = fmin(ymax, R.H - 1.0);
+                    }
+                    if (oob) { status = kOutOfBounds; zncc_out = 0.0f; break; }
+                }
+                // ---- deformed coefficients: LDS window if the taps fit, else global
+                // taps of every warped point; the 1e-3 px slack covers the FP32 rounding of
+                // the per-pixel coordinates (far below it) so no tap leaves the window
+                const int tx0 = static_cast<int>(floor(xmin - 1e-3)) - 1, tx1 = static_cast<int>(floor(xmax + 1e-3)) + 2;
+                const int ty0 = static_cast<int>(floor(ymin - 1e-3)) - 1, ty1 = static_cast<int>(floor(ymax + 1e-3)) + 2;
+                const bool fits = (tx1 - tx0 < ts) && (ty1 - ty0 < ts) && (R.W + 2 * kPad >= ts) &&
+                                  (R.H + 2 * kPad >= ts);
+                if (fits && !(tx0 >= tox && tx1 < tox + ts && ty0 >= toy && ty1 < toy + ts)) {
+                    // split the spare room evenly: the window covers [tx0, tx1] x [ty0, ty1]
+                    int ox = tx0 - (ts - (tx1 - tx0 + 1)) / 2;
+                    int oy = ty0 - (ts - (ty1 - ty0 + 1)) / 2;
+                    ox = max(-kPad, min(ox, R.W + kPad - ts));
+                    oy = max(-kPad, min(oy, R.H + kPad - ts));
+                    tox = ox;
+                    toy = oy;
+                    __syncthreads();   // previous window no longer read
+                    for (int e = t; e < ts * ts; e += T) {
+                        const int r = e / ts, c = e - r * ts;
+                        const int64_t go = static_cast<int64_t>(oy + r) * F.dpitch + (ox + c);
+                        tile[e] = half ? to_f32(static_cast<const __half *>(F.dcoef)[go])
+                                       : static_cast<const float *>(F.dcoef)[go];
+                    }
+                    __syncthreads();
+                }
+                // local frame: LDS window origin, or a point near the subset for global reads
+                const int ox = fits ? tox : static_cast<int>(floor(xc + p[0])) - h - 4;
+                const int oy = fits ? toy : static_cast<int>(floor(yc + p[1])) - h - 4;
+                const float A0 = static_cast<float>(static_cast<double>(xc - ox) + p[0]);
+                const float A1 = static_cast<float>(1.0 + p[2]);
+                const float A2 = static_cast<float>(p[3]);
+                const float B0 = static_cast<float>(static_cast<double>(yc - oy) + p[1]);
+                const float B1 = static_cast<float>(p[4]);
+                const float B2 = static_cast<float>(1.0 + p[5]);
+                float Q[6];
+                if constexpr (NP == 12) {
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) Q[q] = static_cast<float>(p[6 + q]);
+                }
+                float s[NS];
+#pragma unroll
+                for (int i = 0; i < NS; ++i) s[i] = 0.0f;
+#pragma unroll
+                for (int j = 0; j < P; ++j) {
+                    if (t + T * j < n) {
+                        const float dx = dxs[j], dy = dys[j];
+                        float X = fmaf(A2, dy, fmaf(A1, dx, A0));
+                        float Y = fmaf(B2, dy, fmaf(B1, dx, B0));
+                        if constexpr (NP == 12) {
+                            const float xx = dx * dx, xy = dx * dy, yy = dy * dy;
+                            X = fmaf(Q[2], yy, fmaf(Q[1], xy, fmaf(Q[0], xx, X)));
+                            Y = fmaf(Q[5], yy, fmaf(Q[4], xy, fmaf(Q[3], xx, Y)));
+                        }
+                        const float fx0 = floorf(X), fy0 = floorf(Y);
+                        float wx0, wx1, wx2, wx3, wy0, wy1, wy2, wy3;
+                        bspline_w(X - fx0, wx0, wx1, wx2, wx3);
+                        bspline_w(Y - fy0, wy0, wy1, wy2, wy3);
+                        const int ixl = static_cast<int>(fx0) - 1, iyl = static_cast<int>(fy0) - 1;
+                        float g;
+                        if (fits) {
+                            g = interp16(tile + iyl * ts + ixl, ts, wx0, wx1, wx2, wx3, wy0, wy1, wy2, wy3);
+                        } else {
+                            const int64_t go = static_cast<int64_t>(oy + iyl) * F.dpitch + (ox + ixl);
+                            if (half)
+                                g = interp16(static_cast<const __half *>(F.dcoef) + go, F.dpitch, wx0, wx1, wx2, wx3,
+                                             wy0, wy1, wy2, wy3);
+                            else
+                                g = interp16(static_cast<const float *>(F.dcoef) + go, F.dpitch, wx0, wx1, wx2, wx3,
+                                             wy0, wy1, wy2, wy3);
+                        }
+                        accumulate<NP>(s, g - fm32, fb[j], gx[j], gy[j], dx, dy);
+                    }
+                }
+                // ---- reduce and solve
+                Acc v[NS];
+#pragma unroll
+                for (int i = 0; i < NS; ++i) v[i] = static_cast<Acc>(s[i]);
+                block_allreduce<T, NS>(v, red, parity);
+                const Acc S0 = v[0], S1 = v[1];
+                const Acc gm = S0 / static_cast<Acc>(n);
+                const Acc dg2 = S1 - S0 * gm;
+                if (isnan(static_cast<double>(dg2))) { status = kNan; break; }
+                const double lev = fmax(1.0, fabs(fm + static_cast<double>(gm)));
+                if (static_cast<double>(dg2) <= n * (kFlatRel * lev) * (kFlatRel * lev)) {
+                    status = kFlatDef;
+                    zncc_out = 0.0f;
+                    break;
+                }
+                const Acc sfg = v[2] - gm * static_cast<Acc>(Sfb);
+                const Acc zn = sfg / sqrt(static_cast<Acc>(df2) * dg2);
+                const Acc ratio = sqrt(static_cast<Acc>(df2) / dg2);
+                Acc b[NP];
+#pragma unroll
+                for (int a = 0; a < NP; ++a)
+                    b[a] = static_cast<Acc>(SJf[a]) - ratio * (v[3 + a] - gm * static_cast<Acc>(SJ[a]));
+                double dp[NP];
+                {
+                    int q = 0;
+                    Acc acc[NP];
+#pragma unroll
+                    for (int a = 0; a < NP; ++a) acc[a] = 0;
+#pragma unroll
+                    for (int a = 0; a < NP; ++a)
+#pragma unroll
+                        for (int c = a; c < NP; ++c) {
+                            const Acc hv = static_cast<Acc>(Hi[q++]);
+                            acc[a] += hv * b[c];
+                            if (c != a) acc[c] += hv * b[a];
+                        }
+#pragma unroll
+                    for (int a = 0; a < NP; ++a) dp[a] = -static_cast<double>(acc[a]);
+                }
+                zncc_out = static_cast<float>(zn);
+                if constexpr (NP == 6) compose_affine(p, dp);
+                else compose_quadratic(p, dp);
+                double nrm = dp[0] * dp[0] + dp[1] * dp[1];
+                {
+                    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+                    for (int a = 2; a < 6; ++a) s1 += dp[a] * dp[a];
+#pragma unroll
+                    for (int a = 6; a < NP; ++a) s2 += dp[a] * dp[a];
+                    nrm += hd * hd * s1 + hd * hd * hd * hd * s2;
+                }
+                bool bad = isnan(static_cast<double>(zn)) || isnan(nrm);
+#pragma unroll
+                for (int a = 0; a < NP; ++a) bad = bad || isnan(p[a]);
+                if (bad) { status = kNan; break; }
+                if (nrm < ip.tol2) {
+                    status = zncc_out >= ip.zncc_min ? kConverged : kLowZncc;
+                    break;
+                }
+            }
+        }
+
+        // ---- results and propagation (one thread)
+        if (t == 0) {
+#pragma unroll
+            for (int j = 0; j < NP; ++j) F.p[j * nn + node] = static_cast<float>(p[j]);
+            F.zncc[node] = zncc_out;
+            F.iters[node] = static_cast<int16_t>(iters);
+            F.status[node] = static_cast<int8_t>(status);
+            cnt_computed += 1;
+            cnt_iters += static_cast<unsigned long long>(iters);
+            if (status == kConverged) {
+                cnt_converged += 1;
+                const uint64_t zkey = static_cast<uint64_t>(ordered_bits(zncc_out)) << 2;
+                // children to the right / left / below / above see this node as their
+                // left (3) / right (2) / upper (1) / lower (0) neighbour
+                const int cxs[4] = {ix + 1, ix - 1, ix, ix};
+                const int cys[4] = {iy, iy, iy + 1, iy - 1};
+                const uint64_t pri[4] = {3, 2, 1, 0};
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    const int cx = cxs[d], cy = cys[d];
+                    if (cx < 0 || cy < 0 || cx >= R.nx || cy >= R.ny) continue;
+                    const int64_t m = static_cast<int64_t>(cy) * R.nx + cx;
+                    if (R.flag[m] < 0) continue;
+                    const int old = atomicCAS(F.wave + m, -1, k + 1);
+                    if (old == -1) {
+                        const int slot = atomicAdd(F.counts + k + 1, 1);
+                        lout[slot] = static_cast<int32_t>(m);
+                        atomicAdd(ip.wave_total + k + 1, 1);
+                    }
+                    if (old == -1 || old == k + 1)
+                        atomicMax(reinterpret_cast<unsigned long long *>(F.pkey + m),
+                                  static_cast<unsigned long long>(zkey | pri[d]));
+                }
+            }
+        }
+    }
+    if (t == 0 && cur_frame >= 0) {
+        unsigned long long *st = frames[cur_frame].stat;
+        atomicAdd(st + 0, cnt_computed);
+        atomicAdd(st + 1, cnt_converged);
+        atomicAdd(st + 2, cnt_iters);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+// ---------------------------------------------------------------------------
+template <int NP, int T, int P>
+static void wave_inst(const RefView &R, const FrameState *F, int nframes, int k, bool f64, const IterParams &ip,
+                      int ts, bool half, int grid, hipStream_t s)
+{
+    const size_t lds = static_cast<size_t>(ts) * ts * sizeof(float);
+    if (f64)
+        k_wave<NP, T, P, true><<<grid, T, lds, s>>>(R, F, nframes, k, ip, ts, half ? 1 : 0);
+    else
+        k_wave<NP, T, P, false><<<grid, T, lds, s>>>(R, F, nframes, k, ip, ts, half ? 1 : 0);
+}
+
+// Pixels per thread for subset size N at T threads: the smallest supported
+// register block holding ceil(N^2 / T) pixels.
+static int pixels_per_thread(int N, int T)
+{
+    const int need = (N * N + T - 1) / T;
+    const int opts[] = {2, 4, 8, 12, 16};
+    for (int o : opts)
+        if (o >= need) return o;
+    return -1;
+}
+
+#define DIC_TP_CASES(NP, X)                                                                                           \
+    X(NP, 64, 4) X(NP, 64, 8) X(NP, 64, 12) X(NP, 64, 16) X(NP, 128, 2) X(NP, 128, 4) X(NP, 128, 8) X(NP, 128, 12)    \
+    X(NP, 128, 16) X(NP, 256, 2) X(NP, 256, 4) X(NP, 256, 8) X(NP, 256, 12) X(NP, 256, 16)
+
+int tile_side(int N)
+{
+    // the warped subset plus 4 taps plus room to drift: 17 px beyond N, rounded to 16
+    return ((N + 17 + 15) / 16) * 16;
+}
+
+bool launch_wave(const RefView &R, const FrameState *F_dev, int nframes, int k, int np, int tps, bool half, bool f64,
+                 const IterParams &ip, int grid, hipStream_t s)
+{
+    const int P = pixels_per_thread(R.N, tps);
+    const int ts = tile_side(R.N);
+#define X(NP_, T_, P_)                                                                                                \
+    if (np == NP_ && tps == T_ && P == P_) {                                                                          \
+        wave_inst<NP_, T_, P_>(R, F_dev, nframes, k, f64, ip, ts, half, grid, s);                                      \
+        return true;                                                                                                   \
+    }
+    DIC_TP_CASES(6, X)
+    DIC_TP_CASES(12, X)
+#undef X
+    return false;
+}
+
+void launch_ref_nodes(const RefView &R, int np, int tps, double *cache, int8_t *flag, hipStream_t s)
+{
+    const int P = pixels_per_thread(R.N, tps);
+#define X(NP_, T_, P_)                                                                                                \
+    if (np == NP_ && tps == T_ && P == P_) {                                                                          \
+        ref_nodes_inst<NP_, T_, P_>(R, cache, flag, s);                                                               \
+        return;                                                                                                        \
+    }
+    DIC_TP_CASES(6, X)
+    DIC_TP_CASES(12, X)
+#undef X
+}
+
+bool supported_tps(int N, int tps)
+{
+    const int P = pixels_per_thread(N, tps);
+    if (P < 0) return false;
+    if (tps == 64 && P < 4) return false;
+    return tps == 64 || tps == 128 || tps == 256;
+}
+
+int wave_grid_hint(int np, int tps, int device)
+{
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    // enough workgroups to keep every SIMD busy with a few subsets each
+    const int per_cu = tps == 64 ? 16 : (tps == 128 ? 8 : 4);
+    (void)np;
+    return cus * per_cu;
+}
+
+} // namespace dicmi

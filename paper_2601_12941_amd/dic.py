@@ -1,0 +1,257 @@
+"""Python binding of the C ABI in include/dic.h (libdicmi.so).
+
+Argument marshalling only: every step of the correlation runs in the HIP
+library.  PyTorch supplies device memory and the stream.  The entry points
+keep the C names (dic_create, dic_set_reference, dic_grid_shape,
+dic_correlate, dic_correlate_batch, dic_get_stats, dic_destroy,
+dic_last_error); `Engine` wraps them for torch tensors.
+
+There is no fallback: if the library is missing or cannot be loaded, every
+call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Iterable, List, Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdicmi.so")
+
+DIC_OK, DIC_E_INVAL, DIC_E_NOMEM, DIC_E_DEVICE, DIC_E_STATE, DIC_E_NOSEED, DIC_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "OK", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_STATE", -5: "E_NOSEED",
+                -6: "E_UNSUPPORTED"}
+PIX_U8, PIX_U16, PIX_F32 = 0, 1, 2
+SHAPE_RIGID, SHAPE_AFFINE, SHAPE_QUADRATIC = 2, 6, 12
+NODE = dict(CONVERGED=0, NOT_REACHED=1, NOT_IN_ROI=2, MAX_ITER=3, LOW_ZNCC=4, OUT_OF_BOUNDS=5, FLAT_REF=6,
+            FLAT_DEF=7, SINGULAR=8, NAN=9)
+
+# exported names, in the order include/dic.h declares them
+EXPORTS = ["dic_create", "dic_set_reference", "dic_grid_shape", "dic_correlate", "dic_correlate_batch",
+           "dic_get_stats", "dic_destroy", "dic_last_error"]
+
+
+class DicImage(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("pitch_bytes", C.c_int64), ("pixel", C.c_int32),
+                ("data", C.c_void_p)]
+
+
+class DicParams(C.Structure):
+    _fields_ = [("subset_size", C.c_int32), ("step", C.c_int32), ("shape", C.c_int32), ("max_iter", C.c_int32),
+                ("tol", C.c_double), ("zncc_min", C.c_double), ("seed_radius", C.c_int32),
+                ("guess_mode", C.c_int32), ("coef_fp16", C.c_int32), ("reduce_fp64", C.c_int32),
+                ("nan_unconverged", C.c_int32), ("threads_per_subset", C.c_int32)]
+
+
+class DicSeed(C.Structure):
+    _fields_ = [("x", C.c_double), ("y", C.c_double), ("u0", C.c_double), ("v0", C.c_double)]
+
+
+class DicResult(C.Structure):
+    _fields_ = [("p", C.c_void_p), ("zncc", C.c_void_p), ("iters", C.c_void_p), ("status", C.c_void_p),
+                ("wave", C.c_void_p)]
+
+
+class DicStats(C.Structure):
+    _fields_ = [("nodes", C.c_int64), ("active", C.c_int64), ("computed", C.c_int64), ("converged", C.c_int64),
+                ("iterations", C.c_int64), ("waves", C.c_int32), ("frames", C.c_int32),
+                ("threads_per_subset", C.c_int32), ("seed_du", C.c_int32), ("seed_dv", C.c_int32),
+                ("ms_total", C.c_double), ("ms_icgn", C.c_double), ("ms_prefilter", C.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libdicmi.so and declare its signatures.  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("the HIP library %s is not built; run paper_2601_12941_amd.build.build()" % path)
+    L = C.CDLL(path)
+    P = C.POINTER
+    L.dic_create.argtypes = [P(C.c_void_p), C.c_int, C.c_void_p]
+    L.dic_set_reference.argtypes = [C.c_void_p, P(DicImage), C.c_void_p, P(DicParams)]
+    L.dic_grid_shape.argtypes = [C.c_void_p] + [P(C.c_int32)] * 5
+    L.dic_correlate.argtypes = [C.c_void_p, P(DicImage), P(DicSeed), C.c_int32, P(DicResult)]
+    L.dic_correlate_batch.argtypes = [C.c_void_p, P(DicImage), C.c_int32, P(DicSeed), C.c_int32, P(DicResult)]
+    L.dic_get_stats.argtypes = [C.c_void_p, P(DicStats)]
+    L.dic_destroy.argtypes = [C.c_void_p]
+    L.dic_last_error.argtypes = [C.c_void_p]
+    L.dic_last_error.restype = C.c_char_p
+    for n in EXPORTS:
+        if n != "dic_last_error":
+            getattr(L, n).restype = C.c_int
+    _lib = L
+    return L
+
+
+class DicError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (STATUS_NAMES.get(code, "?"), code, msg))
+        self.code = code
+
+
+# ---- C-named entry points -------------------------------------------------
+def dic_create(device: int = 0, stream: Optional[int] = None) -> C.c_void_p:
+    ctx = C.c_void_p()
+    rc = load_library().dic_create(C.byref(ctx), int(device), C.c_void_p(stream or 0))
+    if rc != DIC_OK:
+        raise DicError(rc, "dic_create failed")
+    return ctx
+
+
+def dic_last_error(ctx) -> str:
+    m = load_library().dic_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def _check(ctx, rc):
+    if rc != DIC_OK:
+        raise DicError(rc, dic_last_error(ctx))
+
+
+def dic_set_reference(ctx, image: DicImage, roi_ptr: int, params: DicParams):
+    _check(ctx, load_library().dic_set_reference(ctx, C.byref(image), C.c_void_p(roi_ptr or 0), C.byref(params)))
+
+
+def dic_grid_shape(ctx):
+    v = [C.c_int32() for _ in range(5)]
+    _check(ctx, load_library().dic_grid_shape(ctx, *[C.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
+def dic_correlate(ctx, image: DicImage, seeds: Sequence[DicSeed], result: DicResult):
+    arr = (DicSeed * len(seeds))(*seeds)
+    _check(ctx, load_library().dic_correlate(ctx, C.byref(image), arr, len(seeds), C.byref(result)))
+
+
+def dic_correlate_batch(ctx, images: Sequence[DicImage], seeds: Sequence[DicSeed], nseeds: int,
+                        results: Sequence[DicResult]):
+    ims = (DicImage * len(images))(*images)
+    sds = (DicSeed * len(seeds))(*seeds)
+    res = (DicResult * len(results))(*results)
+    _check(ctx, load_library().dic_correlate_batch(ctx, ims, len(images), sds, nseeds, res))
+
+
+def dic_get_stats(ctx) -> dict:
+    s = DicStats()
+    _check(ctx, load_library().dic_get_stats(ctx, C.byref(s)))
+    return {k: getattr(s, k) for k, _ in DicStats._fields_}
+
+
+def dic_destroy(ctx):
+    load_library().dic_destroy(ctx)
+
+
+# ---- torch convenience -----------------------------------------------------
+def _image(t) -> DicImage:
+    import torch
+    if not t.is_cuda:
+        raise ValueError("images must be device tensors")
+    if t.dim() != 2:
+        raise ValueError("images must be 2-D [H][W]")
+    if t.stride(1) != 1:
+        raise ValueError("image rows must be contiguous")
+    if t.dtype == torch.uint8:
+        pix, es = PIX_U8, 1
+    elif t.dtype in (torch.int16, torch.uint16):
+        pix, es = PIX_U16, 2
+    elif t.dtype == torch.float32:
+        pix, es = PIX_F32, 4
+    else:
+        raise ValueError("unsupported image dtype %s" % t.dtype)
+    return DicImage(t.shape[1], t.shape[0], t.stride(0) * es, pix, t.data_ptr())
+
+
+def to_device_image(a, device="cuda"):
+    """numpy image -> device tensor (uint16 data travels as int16 bits)."""
+    import numpy as np
+    import torch
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint16:
+        a = a.view(np.int16)
+    return torch.from_numpy(a).to(device)
+
+
+class Engine:
+    """A library context bound to one device and the current torch stream."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.device = torch.device("cuda", device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.ctx = dic_create(device, self.stream.cuda_stream)
+        self.shape = None
+        self._keep = []
+
+    def close(self):
+        if self.ctx is not None:
+            dic_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_reference(self, ref, roi=None, *, subset_size, step, shape=6, tol=1e-4, max_iter=50, zncc_min=0.7,
+                      seed_radius=8, guess="extrapolate", coef_fp16=False, reduce_fp64=True, nan_unconverged=False,
+                      threads_per_subset=0):
+        prm = DicParams(subset_size, step, shape, max_iter, tol, zncc_min, seed_radius,
+                        1 if guess == "copy" else 0, int(bool(coef_fp16)), int(bool(reduce_fp64)),
+                        int(bool(nan_unconverged)), threads_per_subset)
+        roi_ptr = 0
+        if roi is not None:
+            import torch
+            if roi.dtype != torch.uint8 or not roi.is_cuda or not roi.is_contiguous() or tuple(roi.shape) != tuple(
+                    ref.shape):
+                raise ValueError("roi must be a contiguous uint8 device tensor shaped like the image")
+            roi_ptr = roi.data_ptr()
+        self.ref = ref
+        dic_set_reference(self.ctx, _image(ref), roi_ptr, prm)
+        self.shape = shape
+        self.grid = dic_grid_shape(self.ctx)
+        return self.grid
+
+    def _alloc(self):
+        import torch
+        nx, ny = self.grid[0], self.grid[1]
+        d = self.device
+        out = dict(p=torch.empty((self.shape, ny, nx), dtype=torch.float32, device=d),
+                   zncc=torch.empty((ny, nx), dtype=torch.float32, device=d),
+                   iters=torch.empty((ny, nx), dtype=torch.int16, device=d),
+                   status=torch.empty((ny, nx), dtype=torch.int8, device=d),
+                   wave=torch.empty((ny, nx), dtype=torch.int32, device=d))
+        res = DicResult(out["p"].data_ptr(), out["zncc"].data_ptr(), out["iters"].data_ptr(),
+                        out["status"].data_ptr(), out["wave"].data_ptr())
+        return out, res
+
+    @staticmethod
+    def _seeds(seeds: Iterable) -> List[DicSeed]:
+        return [DicSeed(float(s[0]), float(s[1]), float(s[2]) if len(s) > 2 else 0.0,
+                        float(s[3]) if len(s) > 3 else 0.0) for s in seeds]
+
+    def correlate(self, deformed, seeds):
+        out, res = self._alloc()
+        dic_correlate(self.ctx, _image(deformed), self._seeds(seeds), res)
+        return out
+
+    def correlate_batch(self, frames, seeds):
+        """frames: list of device images; seeds: one list shared by all frames, or one list per frame."""
+        seeds = list(seeds)
+        per_frame = len(seeds) == len(frames) and all(isinstance(s, (list, tuple)) and len(s) > 0 and
+                                                        isinstance(s[0], (list, tuple)) for s in seeds)
+        lists = seeds if per_frame else [seeds] * len(frames)
+        ns = len(lists[0])
+        if any(len(s) != ns for s in lists):
+            raise ValueError("every frame needs the same number of seeds")
+        flat = [sd for s in lists for sd in self._seeds(s)]
+        outs, ress = zip(*[self._alloc() for _ in frames])
+        dic_correlate_batch(self.ctx, [_image(f) for f in frames], flat, ns, list(ress))
+        return list(outs)
+
+    def stats(self) -> dict:
+        return dic_get_stats(self.ctx)

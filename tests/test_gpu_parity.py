@@ -1,0 +1,81 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs, element by element, plus the properties that hold at any
+size (exact zero displacement, determinism, batch == plain)."""
+import numpy as np
+import pytest
+
+from oracle import ST
+from paper_2601_12941_amd import synth
+
+from gpu_common import compare, gpu_run, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def c1():
+    w = synth.workload("c1")
+    return w, w.pair()
+
+
+def test_c1_full_size_parity(c1):
+    # 512^2 u8, subset 21, step 5, affine: 99^2 nodes, several tiles, ragged edges
+    w, pair = c1
+    g, _ = gpu_run(pair, w)
+    o = oracle_run(pair, w)
+    rep = compare(g, o)
+    assert rep["both_converged"] > 9000
+    assert g["stats"]["converged"] == int((g["status"] == ST["CONVERGED"]).sum())
+
+
+def test_c1_fp32_reductions_parity(c1):
+    w, pair = c1
+    g, _ = gpu_run(pair, w, reduce_fp64=False)
+    compare(g, oracle_run(pair, w))
+
+
+@pytest.mark.parametrize("tps", [64, 128, 256])
+def test_c1_every_workgroup_size_parity(c1, tps):
+    w, pair = c1
+    g, _ = gpu_run(pair, w, threads_per_subset=tps)
+    compare(g, oracle_run(pair, w))
+
+
+def test_zero_displacement_is_exactly_zero():
+    w = synth.workload("c1", size=160)
+    pair = w.pair()
+    pair.deformed = pair.ref.copy()
+    g, _ = gpu_run(pair, w)
+    act = g["status"] != ST["NOT_IN_ROI"]
+    assert np.all(g["status"][act] == ST["CONVERGED"])
+    assert np.all(g["p"][:, act] == 0.0)
+    assert np.all(g["iters"][act] == 1)
+    assert np.abs(g["zncc"][act] - 1.0).max() <= 1e-6
+
+
+def test_repeat_runs_are_bitwise_identical(c1):
+    w, pair = c1
+    a, eng = gpu_run(pair, w)
+    b, _ = gpu_run(pair, w, engine=eng)
+    for k in ("p", "zncc", "iters", "status", "wave"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_batch_equals_plain():
+    import torch
+    from paper_2601_12941_amd import dic
+    w = synth.workload("c1", size=256)
+    pair = w.pair()
+    frames = [pair.deformed]
+    for s in (1004, 1005):
+        frames.append(synth.make_pair(w.W, w.H, w.nblobs, w.sigma, w.amp, w.field(), w.noise, w.bits, w.seed_blobs,
+                                      w.seed_noise_ref, s).deformed)
+    eng = dic.Engine(0)
+    roi = torch.from_numpy(pair.roi).cuda()
+    eng.set_reference(dic.to_device_image(pair.ref), roi, **w.params())
+    plain = [eng.correlate(dic.to_device_image(f), w.seeds) for f in frames]
+    batch = eng.correlate_batch([dic.to_device_image(f) for f in frames], w.seeds)
+    torch.cuda.synchronize()
+    for a, b in zip(plain, batch):
+        for k in a:
+            assert torch.equal(a[k], b[k]), k
