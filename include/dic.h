@@ -118,8 +118,10 @@ typedef struct {
     int32_t threads_per_subset;
     int32_t seed_du, seed_dv; /* integer seed shift of the first seed of the last frame */
     double ms_total;        /* device time of the last call (HIP events) */
-    double ms_icgn;         /* device time inside the IC-GN wave kernels */
+    double ms_icgn;         /* device time from the first to the last IC-GN wave kernel */
     double ms_prefilter;    /* device time of the deformed-image prefilter */
+    double ms_wave_kernels; /* device time of the chunks of back-to-back wave launches, host gaps excluded */
+    int32_t wave_launches;  /* IC-GN wave kernel launches of the last call */
 } dic_stats;
 
 /* Create a context on HIP device `device`, ordering its work on `hip_stream`

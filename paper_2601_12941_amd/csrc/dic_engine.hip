@@ -71,6 +71,7 @@ struct dic_ctx {
     int32_t *d_wave_total = nullptr;
     int32_t *h_pinned = nullptr;
     hipEvent_t ev[4] = {};
+    std::vector<hipEvent_t> chunk_ev;
     dic_stats stats{};
 
     size_t coef_elems() const { return static_cast<size_t>(cpitch) * (H + 2 * kPad); }
@@ -245,6 +246,7 @@ dic_status dic_destroy(dic_ctx *c)
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto &e : c->chunk_ev) (void)hipEventDestroy(e);
     delete c;
     return DIC_OK;
 }
@@ -462,30 +464,52 @@ dic_status dic_correlate_batch(dic_ctx *c, const dic_image *defs, int32_t nframe
     ip.zncc_min = static_cast<float>(c->prm.zncc_min);
     ip.guess_copy = c->prm.guess_mode;
     ip.seed_radius = c->prm.seed_radius;
-    ip.wave_total = c->d_wave_total;
     const int grid = wave_grid_hint(c->np, c->tps, c->device);
+    FrameTable table;
+    std::memset(&table, 0, sizeof(table));
+    for (int f = 0; f < nframes; ++f) table.f[f] = c->h_frames[f];
+    table.n = nframes;
     const bool f64 = c->prm.reduce_fp64 != 0;
-    int k = 0, chunk = 4, waves = 0;
+    int k = 0, chunk = 4, waves = 0, nchunk = 0;
     for (;;) {
+        if (static_cast<int>(c->chunk_ev.size()) < 2 * (nchunk + 1)) {
+            hipEvent_t a, b;
+            HIPCHK(hipEventCreate(&a));
+            HIPCHK(hipEventCreate(&b));
+            c->chunk_ev.push_back(a);
+            c->chunk_ev.push_back(b);
+        }
+        HIPCHK(hipEventRecord(c->chunk_ev[2 * nchunk], s));
         for (int j = 0; j < chunk && k <= c->nodes; ++j, ++k)
-            if (!launch_wave(R, c->d_frames, nframes, k, c->np, c->tps, half, f64, ip, grid, s))
+            if (!launch_wave(R, table, k, c->np, c->tps, half, f64, ip, grid, s))
                 FAIL(DIC_E_UNSUPPORTED, "no kernel for shape %d, %d threads, subset %d", c->np, c->tps,
                      c->prm.subset_size);
         HIPCHK(hipGetLastError());
-        // wave_total[k] counts the nodes pushed into wave k (k >= 1)
+        HIPCHK(hipEventRecord(c->chunk_ev[2 * nchunk + 1], s));
+        ++nchunk;
+        // size of the next wave, summed over the frames
+        launch_count_wave(c->d_frames, nframes, k, c->d_wave_total, s);
         HIPCHK(hipMemcpyAsync(c->h_pinned, c->d_wave_total + k, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         if (c->h_pinned[0] == 0 || k > c->nodes) break;
         chunk = std::min(chunk * 2, 64);
     }
     HIPCHK(hipEventRecord(c->ev[3], s));
-    for (int f = 0; f < nframes; ++f)
+    for (int f = 0; f < nframes; ++f) {
+        launch_frame_stats(R, c->h_frames[f], s);
         launch_finalize(R, c->h_frames[f], c->np, c->prm.nan_unconverged != 0, s);
+    }
     HIPCHK(hipGetLastError());
 
-    // counters: number of waves = first empty wave index
-    std::vector<int32_t> wt(k + 1);
-    HIPCHK(hipMemcpyAsync(wt.data(), c->d_wave_total, sizeof(int32_t) * (k + 1), hipMemcpyDeviceToHost, s));
+    // counters: number of waves = first empty wave index (frame 0's counts suffice
+    // per frame; over frames, the waves of the longest frame)
+    std::vector<int32_t> wt(k + 1, 0);
+    for (int f = 0; f < nframes; ++f) {
+        std::vector<int32_t> cf(k + 1);
+        HIPCHK(hipMemcpyAsync(cf.data(), c->frames[f].counts, sizeof(int32_t) * (k + 1), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int q = 0; q <= k; ++q) wt[q] += cf[q];
+    }
     std::vector<unsigned long long> stat(4 * nframes);
     for (int f = 0; f < nframes; ++f)
         HIPCHK(hipMemcpyAsync(stat.data() + 4 * f, c->frames[f].stat, sizeof(unsigned long long) * 4,
@@ -493,7 +517,7 @@ dic_status dic_correlate_batch(dic_ctx *c, const dic_image *defs, int32_t nframe
     double sp[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(sp, c->frames[nframes - 1].seed_p, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    waves = 1;
+    waves = 0;
     while (waves <= k && wt[waves] > 0) ++waves;
     dic_stats S{};
     S.nodes = c->nodes;
@@ -515,6 +539,11 @@ dic_status dic_correlate_batch(dic_ctx *c, const dic_image *defs, int32_t nframe
     S.ms_icgn = ms;
     HIPCHK(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
     S.ms_prefilter = ms;
+    S.wave_launches = k;
+    for (int q = 0; q < nchunk; ++q) {
+        HIPCHK(hipEventElapsedTime(&ms, c->chunk_ev[2 * q], c->chunk_ev[2 * q + 1]));
+        S.ms_wave_kernels += ms;
+    }
     c->stats = S;
     return DIC_OK;
 }

@@ -11,8 +11,9 @@ namespace dicmi {
 // Coefficient arrays carry this many mirrored samples on every side, so that
 // the 4x4 taps of any in-image point (x0-1 .. x0+2) never need index folding.
 constexpr int kPad = 4;
-// Frames one batched launch may carry.
-constexpr int kMaxFrames = 64;
+// Frames one batched launch may carry (the frame table travels in the kernel
+// arguments, which hold at most 4 KiB).
+constexpr int kMaxFrames = 16;
 
 enum NodeStatus : int8_t {
     kConverged = 0,
@@ -57,7 +58,6 @@ struct IterParams {
     float zncc_min;
     int guess_copy;     // 1: copy the neighbour's p, 0: extrapolate
     int seed_radius;
-    int32_t *wave_total; // [waves] nodes pushed into each wave, summed over frames
 };
 
 // Device-resident state of one frame of a (batched) correlation.
@@ -81,6 +81,13 @@ struct FrameState {
     unsigned long long *stat; // [0] computed, [1] converged, [2] iterations
 };
 
+// The frames of one launch, passed by value as a kernel argument: uniform
+// indexing gives scalar loads, and the pointers are known to be global.
+struct FrameTable {
+    FrameState f[kMaxFrames];
+    int n;
+};
+
 // ---- launchers (dic_kernels.hip) -------------------------------------
 void launch_prefilter(const void *src, int64_t src_pitch_bytes, int pixel, int W, int H, float *tmp,
                       int64_t tmp_pitch, void *dst_at_origin, int64_t dst_pitch, bool half, hipStream_t s);
@@ -92,8 +99,10 @@ void launch_seed_search(const RefView &R, const FrameState *F_dev, int nframes, 
                         const int32_t *seed_center_dev, double *zbuf, hipStream_t s);
 void launch_seed_pick(const RefView &R, const FrameState *F_dev, int nframes, int nseeds, int radius,
                       const int32_t *seed_center_dev, const double *zbuf, hipStream_t s);
-bool launch_wave(const RefView &R, const FrameState *F_dev, int nframes, int k, int np, int tps, bool half,
-                 bool f64, const IterParams &ip, int grid, hipStream_t s);
+bool launch_wave(const RefView &R, const FrameTable &F, int k, int np, int tps, bool half, bool f64,
+                 const IterParams &ip, int grid, hipStream_t s);
+void launch_frame_stats(const RefView &R, const FrameState &F, hipStream_t s);
+void launch_count_wave(const FrameState *F_dev, int nframes, int k, int32_t *out, hipStream_t s);
 void launch_finalize(const RefView &R, const FrameState &F, int np, bool nan_unconverged, hipStream_t s);
 int wave_grid_hint(int np, int tps, int device);
 bool supported_tps(int N, int tps);

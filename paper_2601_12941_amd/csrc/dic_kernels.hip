@@ -14,6 +14,7 @@
 // in LDS and re-staged only when the warp drifts out of the staged window.
 #include "dic_internal.h"
 
+#include <algorithm>
 #include <climits>
 #include <float.h>
 #include <math.h>
@@ -381,7 +382,7 @@ __global__ __launch_bounds__(T) void k_ref_nodes(RefView R, double *cache, int8_
             // same expressions as the iteration's dg2 and J^T gbar, so that an
             // identical deformed subset gives a bitwise-zero increment
             const double S0 = v[0], S1 = v[1];
-            const double gm = S0 / n;
+            const double gm = S0 * (1.0 / n);
             const double df2 = S1 - S0 * gm;
             double SJ[NP], SJf[NP];
 #pragma unroll
@@ -617,6 +618,56 @@ __global__ void k_finalize(RefView R, FrameState F, int np)
         for (int j = 0; j < np; ++j) F.p[j * R.nodes + node] = __int_as_float(0x7fc00000);
 }
 
+// Per-frame counters from the results: nodes computed (wave >= 0), converged,
+// and IC-GN iterations; one atomic per block and counter.
+__global__ __launch_bounds__(256) void k_frame_stats(RefView R, FrameState F)
+{
+    unsigned long long a = 0, b = 0, c = 0;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < R.nodes;
+         i += static_cast<int64_t>(gridDim.x) * 256) {
+        a += F.wave[i] >= 0 ? 1 : 0;
+        b += F.status[i] == kConverged ? 1 : 0;
+        c += static_cast<unsigned long long>(F.iters[i]);
+    }
+    for (int m = 1; m < 64; m <<= 1) {
+        a += __shfl_xor(a, m);
+        b += __shfl_xor(b, m);
+        c += __shfl_xor(c, m);
+    }
+    __shared__ unsigned long long part[4][3];
+    if ((threadIdx.x & 63) == 0) {
+        part[threadIdx.x >> 6][0] = a;
+        part[threadIdx.x >> 6][1] = b;
+        part[threadIdx.x >> 6][2] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const unsigned long long v = part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] +
+                                     part[3][threadIdx.x];
+        atomicAdd(F.stat + threadIdx.x, v);
+    }
+}
+
+void launch_frame_stats(const RefView &R, const FrameState &F, hipStream_t s)
+{
+    const int64_t blocks = std::min<int64_t>((R.nodes + 255) / 256, 1024);
+    k_frame_stats<<<static_cast<unsigned>(blocks), 256, 0, s>>>(R, F);
+}
+
+// Size of wave k summed over the frames (read by the host once per chunk).
+__global__ void k_count_wave(const FrameState *frames, int nframes, int k, int32_t *out)
+{
+    if (threadIdx.x != 0) return;
+    int acc = 0;
+    for (int f = 0; f < nframes; ++f) acc += frames[f].counts[k];
+    out[k] = acc;
+}
+
+void launch_count_wave(const FrameState *F_dev, int nframes, int k, int32_t *out, hipStream_t s)
+{
+    k_count_wave<<<1, 64, 0, s>>>(F_dev, nframes, k, out);
+}
+
 void launch_finalize(const RefView &R, const FrameState &F, int np, bool nan_unconverged, hipStream_t s)
 {
     if (!nan_unconverged) return;
@@ -633,7 +684,8 @@ __device__ __forceinline__ void compose_affine(double (&p)[6], const double (&d)
 {
     const double a = 1.0 + d[2], b = d[3], c = d[4], e = 1.0 + d[5];
     const double det = a * e - b * c;
-    const double r = 1.0 / det;
+    // the reciprocal scales terms that are differences of order |dp|: FP32 suffices
+    const double r = static_cast<double>(1.0f / static_cast<float>(det));
     // translation part of M(dp)^{-1}: -(M2^{-1}) (d0, d1)
     const double tx = (b * d[1] - e * d[0]) * r;
     const double ty = (c * d[0] - a * d[1]) * r;
@@ -721,22 +773,25 @@ __device__ __forceinline__ void compose_quadratic(double (&p)[12], const double 
 // One frontier wave: every subset of wave k of every frame.
 // ---------------------------------------------------------------------------
 template <int NP, int T, int P, bool F64>
-__global__ __launch_bounds__(T) void k_wave(RefView R, const FrameState *__restrict__ frames, int nframes, int k,
-                                            IterParams ip, int ts, int half)
+__global__ __launch_bounds__(T) void k_wave(RefView R, const FrameTable frames, int k, IterParams ip, int ts,
+                                            int half)
 {
     using Acc = typename std::conditional<F64, double, float>::type;
     constexpr int NS = 3 + NP;
     constexpr int NH = NP * (NP + 1) / 2;
+    constexpr int NC = 3 + 2 * NP + NH;   // per-node reference cache slots
     extern __shared__ float tile[];  // ts * ts deformed coefficients
     __shared__ Acc red[2 * (T / 64) * NS];
     __shared__ int prefix[kMaxFrames + 1];
+    __shared__ double cache[NC];      // this subset's reference cache
+    const int nframes = frames.n;
 
     const int t = threadIdx.x;
     if (t == 0) {
         int acc = 0;
         for (int f = 0; f < nframes; ++f) {
             prefix[f] = acc;
-            acc += frames[f].counts[k];
+            acc += frames.f[f].counts[k];
         }
         prefix[nframes] = acc;
     }
@@ -745,6 +800,7 @@ __global__ __launch_bounds__(T) void k_wave(RefView R, const FrameState *__restr
     if (static_cast<int>(blockIdx.x) >= total) return;
 
     const int N = R.N, h = (N - 1) / 2, n = N * N;
+    const double inv_n = 1.0 / n;
     const int64_t nn = R.nodes;
     float dxs[P], dys[P];
 #pragma unroll
@@ -754,28 +810,37 @@ __global__ __launch_bounds__(T) void k_wave(RefView R, const FrameState *__restr
         dys[j] = static_cast<float>(i / N - h);
     }
     int parity = 0;
-    unsigned long long cnt_computed = 0, cnt_converged = 0, cnt_iters = 0;
-    int cur_frame = -1;
 
     for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
         int f = 0;
         while (f + 1 < nframes && prefix[f + 1] <= gi) ++f;
         f = __builtin_amdgcn_readfirstlane(f);
-        if (f != cur_frame && cur_frame >= 0 && t == 0) {
-            unsigned long long *st = frames[cur_frame].stat;
-            atomicAdd(st + 0, cnt_computed);
-            atomicAdd(st + 1, cnt_converged);
-            atomicAdd(st + 2, cnt_iters);
-            cnt_computed = cnt_converged = cnt_iters = 0;
-        }
-        cur_frame = f;
-        const FrameState &F = frames[f];
+        const FrameState &F = frames.f[f];
         const int li = __builtin_amdgcn_readfirstlane(gi - prefix[f]);
         const int32_t *lin = (k & 1) ? F.list1 : F.list0;
         int32_t *lout = (k & 1) ? F.list0 : F.list1;
         const int node = __builtin_amdgcn_readfirstlane(lin[li]);
         const int ix = node % R.nx, iy = node / R.nx;
         const int xc = h + ix * R.step, yc = h + iy * R.step;
+
+        // ---- everything the subset needs from memory is requested up front; only
+        // the parent's parameters wait for the parent key
+        const int8_t rf = R.flag[node];
+        const uint64_t key = k > 0 ? F.pkey[node] : 0;
+        __syncthreads();   // the previous subset is done with the LDS cache and window
+        for (int q = t; q < NC; q += T) cache[q] = R.cache[static_cast<int64_t>(q) * nn + node];
+        float fb[P], gx[P], gy[P];
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            fb[j] = gx[j] = gy[j] = 0.0f;
+            if (t + T * j < n) {
+                const int64_t o = static_cast<int64_t>(yc + static_cast<int>(dys[j])) * R.ppitch + xc +
+                                  static_cast<int>(dxs[j]);
+                fb[j] = R.pf[o];
+                gx[j] = R.pfx[o];
+                gy[j] = R.pfy[o];
+            }
+        }
 
         // ---- initial guess
         double p[NP];
@@ -785,7 +850,7 @@ __global__ __launch_bounds__(T) void k_wave(RefView R, const FrameState *__restr
             p[0] = F.seed_p[2 * li];
             p[1] = F.seed_p[2 * li + 1];
         } else {
-            const uint32_t dir = static_cast<uint32_t>(F.pkey[node] & 3u);
+            const uint32_t dir = static_cast<uint32_t>(key & 3u);
             // priority 3: parent on the left, 2: right, 1: above, 0: below
             // (clamped: a listed node always has a key, the clamp only guards the read)
             const int px = min(max(ix + (dir == 3 ? -1 : (dir == 2 ? 1 : 0)), 0), R.nx - 1);
@@ -815,35 +880,14 @@ __global__ __launch_bounds__(T) void k_wave(RefView R, const FrameState *__restr
         int status = kMaxIter;
         int iters = 0;
         float zncc_out = 0.0f;
-        const int8_t rf = R.flag[node];
+        __syncthreads();   // cache visible to every wavefront
         if (rf != 0) {
             status = rf;
         } else {
-            // ---- reference cache and per-pixel reference data
-            const double fm = R.cache[node];
-            const double df2 = R.cache[nn + node];
-            const double Sfb = R.cache[2 * nn + node];
-            double SJ[NP], SJf[NP], Hi[NH];
+            const float fm32 = static_cast<float>(cache[0]);
 #pragma unroll
-            for (int a = 0; a < NP; ++a) {
-                SJ[a] = R.cache[(3 + a) * nn + node];
-                SJf[a] = R.cache[(3 + NP + a) * nn + node];
-            }
-#pragma unroll
-            for (int q = 0; q < NH; ++q) Hi[q] = R.cache[(3 + 2 * NP + q) * nn + node];
-            const float fm32 = static_cast<float>(fm);
-            float fb[P], gx[P], gy[P];
-#pragma unroll
-            for (int j = 0; j < P; ++j) {
-                fb[j] = gx[j] = gy[j] = 0.0f;
-                if (t + T * j < n) {
-                    const int64_t o = static_cast<int64_t>(yc + static_cast<int>(dys[j])) * R.ppitch + xc +
-                                      static_cast<int>(dxs[j]);
-                    fb[j] = R.pf[o] - fm32;
-                    gx[j] = R.pfx[o];
-                    gy[j] = R.pfy[o];
-                }
-            }
+            for (int j = 0; j < P; ++j)
+                if (t + T * j < n) fb[j] -= fm32;
             const double hd = static_cast<double>(h);
             int tox = INT_MIN / 2, toy = INT_MIN / 2;   // staged window origin (global sample coords)
 
@@ -903,11 +947,45 @@ __global__ __launch_bounds__(T) void k_wave(RefView R, const FrameState *__restr
                     tox = ox;
                     toy = oy;
                     __syncthreads();   // previous window no longer read
-                    for (int e = t; e < ts * ts; e += T) {
-                        const int r = e / ts, c = e - r * ts;
-                        const int64_t go = static_cast<int64_t>(oy + r) * F.dpitch + (ox + c);
-                        tile[e] = half ? to_f32(static_cast<const __half *>(F.dcoef)[go])
-                                       : static_cast<const float *>(F.dcoef)[go];
+                    if (!half) {
+                        // each wavefront fills 64 consecutive window elements per request,
+                        // straight into LDS (no registers, all requests in flight at once)
+                        const float *g = static_cast<const float *>(F.dcoef);
+                        const int lane = t & 63;
+                        const int e_first = (t & ~63);
+                        int e = e_first + lane;
+                        int r = e / ts, c = e - (e / ts) * ts;
+                        const int dr = T / ts, dc = T - (T / ts) * ts;
+                        for (int e0 = e_first; e0 < ts * ts; e0 += T) {
+                            if (e < ts * ts) {
+                                const float *src = g + static_cast<int64_t>(oy + r) * F.dpitch + (ox + c);
+                                __builtin_amdgcn_global_load_lds(
+                                    (const __attribute__((address_space(1))) void *)(src),
+                                    (__attribute__((address_space(3))) void *)(tile + e0), 4, 0, 0);
+                            }
+                            e += T;
+                            r += dr;
+                            c += dc;
+                            if (c >= ts) {
+                                c -= ts;
+                                ++r;
+                            }
+                        }
+                        __builtin_amdgcn_s_waitcnt(0);
+                    } else {
+                        // FP16 storage: widen to FP32 on the way into LDS
+                        const int dr = T / ts, dc = T - (T / ts) * ts;
+                        int r = t / ts, c = t - (t / ts) * ts;
+                        for (int e = t; e < ts * ts; e += T) {
+                            const int64_t go = static_cast<int64_t>(oy + r) * F.dpitch + (ox + c);
+                            tile[e] = to_f32(static_cast<const __half *>(F.dcoef)[go]);
+                            r += dr;
+                            c += dc;
+                            if (c >= ts) {
+                                c -= ts;
+                                ++r;
+                            }
+                        }
                     }
                     __syncthreads();
                 }
@@ -965,22 +1043,27 @@ __global__ __launch_bounds__(T) void k_wave(RefView R, const FrameState *__restr
                 for (int i = 0; i < NS; ++i) v[i] = static_cast<Acc>(s[i]);
                 block_allreduce<T, NS>(v, red, parity);
                 const Acc S0 = v[0], S1 = v[1];
-                const Acc gm = S0 / static_cast<Acc>(n);
+                const Acc gm = S0 * static_cast<Acc>(inv_n);
                 const Acc dg2 = S1 - S0 * gm;
                 if (isnan(static_cast<double>(dg2))) { status = kNan; break; }
-                const double lev = fmax(1.0, fabs(fm + static_cast<double>(gm)));
+                const double lev = fmax(1.0, fabs(cache[0] + static_cast<double>(gm)));
                 if (static_cast<double>(dg2) <= n * (kFlatRel * lev) * (kFlatRel * lev)) {
                     status = kFlatDef;
                     zncc_out = 0.0f;
                     break;
                 }
-                const Acc sfg = v[2] - gm * static_cast<Acc>(Sfb);
-                const Acc zn = sfg / sqrt(static_cast<Acc>(df2) * dg2);
-                const Acc ratio = sqrt(static_cast<Acc>(df2) / dg2);
+                // The sums cancel in FP64 (or FP32); the ratio df/dg and the ZNCC need only
+                // FP32 accuracy: an FP32 ratio moves b by ~1e-7 of |sum J fbar|, i.e. the
+                // increment by ~1e-8 px.  Equal reference and deformed sums give ratio 1
+                // and ZNCC 1 exactly.
+                const Acc sfg = v[2] - gm * static_cast<Acc>(cache[2]);
+                const float ratio_f = sqrtf(static_cast<float>(cache[1]) / static_cast<float>(dg2));
+                const float zn = static_cast<float>(sfg) / (static_cast<float>(dg2) * ratio_f);
+                const Acc ratio = static_cast<Acc>(ratio_f);
                 Acc b[NP];
 #pragma unroll
                 for (int a = 0; a < NP; ++a)
-                    b[a] = static_cast<Acc>(SJf[a]) - ratio * (v[3 + a] - gm * static_cast<Acc>(SJ[a]));
+                    b[a] = static_cast<Acc>(cache[3 + NP + a]) - ratio * (v[3 + a] - gm * static_cast<Acc>(cache[3 + a]));
                 double dp[NP];
                 {
                     int q = 0;
@@ -991,14 +1074,15 @@ __global__ __launch_bounds__(T) void k_wave(RefView R, const FrameState *__restr
                     for (int a = 0; a < NP; ++a)
 #pragma unroll
                         for (int c = a; c < NP; ++c) {
-                            const Acc hv = static_cast<Acc>(Hi[q++]);
+                            const Acc hv = static_cast<Acc>(cache[3 + 2 * NP + q]);
+                            ++q;
                             acc[a] += hv * b[c];
                             if (c != a) acc[c] += hv * b[a];
                         }
 #pragma unroll
                     for (int a = 0; a < NP; ++a) dp[a] = -static_cast<double>(acc[a]);
                 }
-                zncc_out = static_cast<float>(zn);
+                zncc_out = zn;
                 if constexpr (NP == 6) compose_affine(p, dp);
                 else compose_quadratic(p, dp);
                 double nrm = dp[0] * dp[0] + dp[1] * dp[1];
@@ -1010,7 +1094,7 @@ __global__ __launch_bounds__(T) void k_wave(RefView R, const FrameState *__restr
                     for (int a = 6; a < NP; ++a) s2 += dp[a] * dp[a];
                     nrm += hd * hd * s1 + hd * hd * hd * hd * s2;
                 }
-                bool bad = isnan(static_cast<double>(zn)) || isnan(nrm);
+                bool bad = isnan(zn) || isnan(nrm);
 #pragma unroll
                 for (int a = 0; a < NP; ++a) bad = bad || isnan(p[a]);
                 if (bad) { status = kNan; break; }
@@ -1021,47 +1105,43 @@ __global__ __launch_bounds__(T) void k_wave(RefView R, const FrameState *__restr
             }
         }
 
-        // ---- results and propagation (one thread)
+        // ---- results (one thread) and propagation (one lane per direction)
         if (t == 0) {
 #pragma unroll
             for (int j = 0; j < NP; ++j) F.p[j * nn + node] = static_cast<float>(p[j]);
             F.zncc[node] = zncc_out;
             F.iters[node] = static_cast<int16_t>(iters);
             F.status[node] = static_cast<int8_t>(status);
-            cnt_computed += 1;
-            cnt_iters += static_cast<unsigned long long>(iters);
-            if (status == kConverged) {
-                cnt_converged += 1;
-                const uint64_t zkey = static_cast<uint64_t>(ordered_bits(zncc_out)) << 2;
-                // children to the right / left / below / above see this node as their
-                // left (3) / right (2) / upper (1) / lower (0) neighbour
-                const int cxs[4] = {ix + 1, ix - 1, ix, ix};
-                const int cys[4] = {iy, iy, iy + 1, iy - 1};
-                const uint64_t pri[4] = {3, 2, 1, 0};
-#pragma unroll
-                for (int d = 0; d < 4; ++d) {
-                    const int cx = cxs[d], cy = cys[d];
-                    if (cx < 0 || cy < 0 || cx >= R.nx || cy >= R.ny) continue;
-                    const int64_t m = static_cast<int64_t>(cy) * R.nx + cx;
-                    if (R.flag[m] < 0) continue;
-                    const int old = atomicCAS(F.wave + m, -1, k + 1);
-                    if (old == -1) {
-                        const int slot = atomicAdd(F.counts + k + 1, 1);
-                        lout[slot] = static_cast<int32_t>(m);
-                        atomicAdd(ip.wave_total + k + 1, 1);
+        }
+        if (status == kConverged && t < 64) {
+            // lane d (< 4) visits the neighbour in direction d: right, left, below,
+            // above.  That child sees this node as its left (3), right (2), upper
+            // (1) or lower (0) neighbour: the tie-break priority in its parent key.
+            int64_t m = -1;
+            bool inserted = false;
+            if (t < 4) {
+                const int cx = ix + (t == 0 ? 1 : (t == 1 ? -1 : 0));
+                const int cy = iy + (t == 2 ? 1 : (t == 3 ? -1 : 0));
+                if (cx >= 0 && cy >= 0 && cx < R.nx && cy < R.ny) {
+                    m = static_cast<int64_t>(cy) * R.nx + cx;
+                    if (R.flag[m] >= 0) {
+                        const int old = atomicCAS(F.wave + m, -1, k + 1);
+                        inserted = old == -1;
+                        if (old == -1 || old == k + 1)
+                            atomicMax(reinterpret_cast<unsigned long long *>(F.pkey + m),
+                                      static_cast<unsigned long long>(
+                                          (static_cast<uint64_t>(ordered_bits(zncc_out)) << 2) | (3u - t)));
                     }
-                    if (old == -1 || old == k + 1)
-                        atomicMax(reinterpret_cast<unsigned long long *>(F.pkey + m),
-                                  static_cast<unsigned long long>(zkey | pri[d]));
                 }
             }
+            const uint64_t bal = __ballot(inserted);
+            if (bal != 0) {
+                int base = 0;
+                if (t == 0) base = atomicAdd(F.counts + k + 1, __popcll(bal));
+                base = __shfl(base, 0);
+                if (inserted) lout[base + __popcll(bal & ((1ull << t) - 1))] = static_cast<int32_t>(m);
+            }
         }
-    }
-    if (t == 0 && cur_frame >= 0) {
-        unsigned long long *st = frames[cur_frame].stat;
-        atomicAdd(st + 0, cnt_computed);
-        atomicAdd(st + 1, cnt_converged);
-        atomicAdd(st + 2, cnt_iters);
     }
 }
 
@@ -1069,14 +1149,14 @@ __global__ __launch_bounds__(T) void k_wave(RefView R, const FrameState *__restr
 // dispatch
 // ---------------------------------------------------------------------------
 template <int NP, int T, int P>
-static void wave_inst(const RefView &R, const FrameState *F, int nframes, int k, bool f64, const IterParams &ip,
-                      int ts, bool half, int grid, hipStream_t s)
+static void wave_inst(const RefView &R, const FrameTable &F, int k, bool f64, const IterParams &ip, int ts, bool half,
+                      int grid, hipStream_t s)
 {
     const size_t lds = static_cast<size_t>(ts) * ts * sizeof(float);
     if (f64)
-        k_wave<NP, T, P, true><<<grid, T, lds, s>>>(R, F, nframes, k, ip, ts, half ? 1 : 0);
+        k_wave<NP, T, P, true><<<grid, T, lds, s>>>(R, F, k, ip, ts, half ? 1 : 0);
     else
-        k_wave<NP, T, P, false><<<grid, T, lds, s>>>(R, F, nframes, k, ip, ts, half ? 1 : 0);
+        k_wave<NP, T, P, false><<<grid, T, lds, s>>>(R, F, k, ip, ts, half ? 1 : 0);
 }
 
 // Pixels per thread for subset size N at T threads: the smallest supported
@@ -1100,14 +1180,14 @@ int tile_side(int N)
     return ((N + 17 + 15) / 16) * 16;
 }
 
-bool launch_wave(const RefView &R, const FrameState *F_dev, int nframes, int k, int np, int tps, bool half, bool f64,
+bool launch_wave(const RefView &R, const FrameTable &F, int k, int np, int tps, bool half, bool f64,
                  const IterParams &ip, int grid, hipStream_t s)
 {
     const int P = pixels_per_thread(R.N, tps);
     const int ts = tile_side(R.N);
 #define X(NP_, T_, P_)                                                                                                \
     if (np == NP_ && tps == T_ && P == P_) {                                                                          \
-        wave_inst<NP_, T_, P_>(R, F_dev, nframes, k, f64, ip, ts, half, grid, s);                                      \
+        wave_inst<NP_, T_, P_>(R, F, k, f64, ip, ts, half, grid, s);                                      \
         return true;                                                                                                   \
     }
     DIC_TP_CASES(6, X)

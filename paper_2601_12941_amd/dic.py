@@ -56,7 +56,8 @@ class DicStats(C.Structure):
     _fields_ = [("nodes", C.c_int64), ("active", C.c_int64), ("computed", C.c_int64), ("converged", C.c_int64),
                 ("iterations", C.c_int64), ("waves", C.c_int32), ("frames", C.c_int32),
                 ("threads_per_subset", C.c_int32), ("seed_du", C.c_int32), ("seed_dv", C.c_int32),
-                ("ms_total", C.c_double), ("ms_icgn", C.c_double), ("ms_prefilter", C.c_double)]
+                ("ms_total", C.c_double), ("ms_icgn", C.c_double), ("ms_prefilter", C.c_double),
+                ("ms_wave_kernels", C.c_double), ("wave_launches", C.c_int32)]
 
 
 _lib = None
