@@ -10,7 +10,9 @@ A step is one batched pass of the whole path (deformed-image prefilter, seed
 search, every frontier wave of IC-GN, output) over a batch of B deformed
 frames of that pair against the resident reference; `value` is converged
 subsets per second over the K timed steps.  The plain (one frame per call)
-engine is timed beside it, with its p50/p99 pair latency.
+engine is timed beside it, with its p50/p99 pair latency.  The two forms use
+their own launch shapes (threads per subset: 64 for the batched form, which
+is throughput-bound; 128 for the plain form, which is latency-bound).
 
 Prints one JSON line.
 """
@@ -63,18 +65,50 @@ def cpu_baseline(ref, deformed, roi, w, crop):
                       "OpenMP over the nodes of each wave)" % (crop, crop, conv, dt)}
 
 
+def profiled_traffic():
+    """HBM bytes per batched k_wave launch from the committed FETCH_SIZE / WRITE_SIZE
+    counter runs, if they were taken on the kernel source that is built now."""
+    import hashlib
+    rec_path = os.path.join(ROOT, "profiles", "k_wave_2048_batched_traffic.json")
+    src = os.path.join(ROOT, "paper_2601_12941_amd", "csrc", "dic_kernels.hip")
+    try:
+        rec = json.load(open(rec_path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    return rec["traffic_bytes_per_launch"] if rec.get("source_sha256") == sha else None
+
+
+def copy_probe(mib=256, reps=3):
+    """A device-to-device copy of known size: its FETCH_SIZE / WRITE_SIZE counters
+    read `mib` MiB each per dispatch on an exact counter."""
+    import torch
+    x = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": mib * (1 << 20), "reps": reps}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=8, help="deformed frames per batched step")
+    ap.add_argument("--batch", type=int, default=16, help="deformed frames per batched step")
     ap.add_argument("--latency-runs", type=int, default=30, help="plain single-frame calls for p50/p99")
     ap.add_argument("--size", type=int, default=2048)
     ap.add_argument("--fp32-reductions", action="store_true")
-    ap.add_argument("--tps", type=int, default=0, help="threads per subset (0 = library default)")
-    ap.add_argument("--cpu-crop", type=int, default=1024, help="oracle sample window (0 = skip)")
+    ap.add_argument("--tps", type=int, default=64, help="threads per subset, batched form")
+    ap.add_argument("--plain-tps", type=int, default=128, help="threads per subset, plain form")
+    ap.add_argument("--cpu-crop", type=int, default=2048, help="oracle sample window (0 = skip)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 256 MiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
@@ -99,6 +133,8 @@ def main():
     eng.set_reference(d_ref, d_roi, **prm)
     torch.cuda.synchronize()
     t_ref = time.perf_counter() - t0
+    peng = dic.Engine(0)
+    peng.set_reference(d_ref, d_roi, **{**prm, "threads_per_subset": args.plain_tps})
     seeds = w.seeds
 
     # ---- batched steps
@@ -123,17 +159,17 @@ def main():
     value = conv / t_batch
 
     # ---- plain single-frame calls: throughput and pair latency
-    eng.correlate(d_frames[0], seeds)
+    peng.correlate(d_frames[0], seeds)
     torch.cuda.synchronize()
     lat = []
     pconv = 0
     for i in range(args.latency_runs):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        eng.correlate(d_frames[i % len(d_frames)], seeds)
+        peng.correlate(d_frames[i % len(d_frames)], seeds)
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - t1)
-        pconv += eng.stats()["converged"]
+        pconv += peng.stats()["converged"]
     plain_rate = pconv / sum(lat)
     lat_ms = np.array(lat) * 1e3
 
@@ -143,7 +179,8 @@ def main():
     avg_launch_ms = kern_ms / max(1, launches)
     achieved = flops / (kern_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": "k_wave (IC-GN frontier wave)", "achieved": achieved,
-                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                "traffic": profiled_traffic() if args.batch == 16 and args.size == 2048 else None,
                 "flop_per_px_iter": FLOP_PER_PX_IT[w.shape], "avg_launch_us": avg_launch_ms * 1e3,
                 "launches_per_step": launches / args.steps}
 
@@ -169,7 +206,8 @@ def main():
                    "size": args.size, "subset": N, "step": w.step, "nodes": last["nodes"], "active": last["active"],
                    "frames_per_step": args.batch, "threads_per_subset": last["threads_per_subset"]},
         "plain": {"value": plain_rate, "unit": "converged subsets/s", "latency_ms_p50": float(np.percentile(lat_ms, 50)),
-                  "latency_ms_p99": float(np.percentile(lat_ms, 99)), "runs": args.latency_runs},
+                  "latency_ms_p99": float(np.percentile(lat_ms, 99)), "runs": args.latency_runs,
+                  "threads_per_subset": args.plain_tps},
         "batched_over_plain": value / plain_rate,
         "waves_per_frame": last["waves"],
         "iterations_per_subset": iters / max(1, conv),
@@ -180,6 +218,7 @@ def main():
     }
     print(json.dumps(rec))
     eng.close()
+    peng.close()
 
 
 if __name__ == "__main__":
