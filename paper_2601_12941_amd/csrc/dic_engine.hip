@@ -292,7 +292,7 @@ dic_status dic_set_reference(dic_ctx *c, const dic_image *ref, const uint8_t *ro
     if (ref->width < p.subset_size || ref->height < p.subset_size)
         FAIL(DIC_E_INVAL, "image %dx%d smaller than subset %d", ref->width, ref->height, p.subset_size);
     int tps = p.threads_per_subset;
-    if (tps == 0) tps = p.subset_size <= 21 ? 64 : (p.subset_size <= 45 ? 128 : 256);
+    if (tps == 0) tps = p.subset_size <= 23 ? 64 : (p.subset_size <= 37 ? 128 : 256);
     if (!supported_tps(p.subset_size, tps))
         FAIL(DIC_E_INVAL, "threads_per_subset %d unsupported for subset %d", tps, p.subset_size);
     if (p.shape == DIC_SHAPE_QUADRATIC && tps == 64 && p.subset_size > 21)

@@ -96,18 +96,71 @@ __device__ __forceinline__ uint32_t ordered_bits(float f)
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-// All-reduce of NV values over the T threads of a workgroup.  Within a
-// wavefront an xor butterfly leaves every lane with bitwise the same total;
-// wavefront totals are then summed in a fixed order from LDS (double buffered
-// by `parity`, since one barrier separates consecutive uses).
+// Value of the lane chosen by DPP control CTRL (quad_perm, row mirrors), per 32-bit half.
+template <int CTRL>
+__device__ __forceinline__ double dpp_read(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_read(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// v + (v of the partner lane) where the partner sits in the other 16-lane row of a row
+// pair (permlane16 swap) or in the other 32-lane half (permlane32 swap).  The swap
+// returns the even-row (lower-half) value in one result and the odd-row (upper-half)
+// value in the other on every lane, so their sum is formed in the same order everywhere.
+__device__ __forceinline__ float pair_sum16(float v)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(v), __float_as_int(v), false, false);
+    return __int_as_float(r[0]) + __int_as_float(r[1]);
+}
+__device__ __forceinline__ float pair_sum32(float v)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_int(v), __float_as_int(v), false, false);
+    return __int_as_float(r[0]) + __int_as_float(r[1]);
+}
+__device__ __forceinline__ double pair_sum16(double v)
+{
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+__device__ __forceinline__ double pair_sum32(double v)
+{
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+
+// Sum over the 64 lanes of a wavefront, left in every lane.  Each step adds the value
+// of a partner lane under an involution (quad xor 1, quad xor 2, half-row mirror, row
+// mirror, row pairs, halves), so both partners form the same sum: every lane ends
+// with bitwise the same total.  No LDS traffic.
+template <typename V>
+__device__ __forceinline__ V wave_allreduce(V v)
+{
+    v += dpp_read<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_read<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_read<0x141>(v);  // row_half_mirror
+    v += dpp_read<0x140>(v);  // row_mirror
+    v = pair_sum16(v);
+    v = pair_sum32(v);
+    return v;
+}
+
+// All-reduce of NV values over the T threads of a workgroup: wavefront totals, then
+// summed in a fixed order from LDS (double buffered by `parity`, since one barrier
+// separates consecutive uses).
 template <int T, int NV, typename V>
 __device__ __forceinline__ void block_allreduce(V (&v)[NV], V *red, int &parity)
 {
 #pragma unroll
-    for (int m = 1; m < 64; m <<= 1) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) v[i] += __shfl_xor(v[i], m);
-    }
+    for (int i = 0; i < NV; ++i) v[i] = wave_allreduce(v[i]);
     if constexpr (T > 64) {
         constexpr int NW = T / 64;
         V *buf = red + parity * NW * NV;
@@ -127,6 +180,21 @@ __device__ __forceinline__ void block_allreduce(V (&v)[NV], V *red, int &parity)
         parity ^= 1;
     }
 }
+
+// Subset pixels over the T threads of a workgroup, column per thread: thread t owns
+// column c = t mod N of the subset and rows r0 + R j (r0 = t div N, R = T div N rows
+// per pass) for j < P; threads t >= N R own nothing.  Offsets from the subset centre:
+// dx = c - h (fixed per thread), dy = r0 - h + R j.
+struct Columns {
+    int c, r0, R, jmax;   // jmax: number of valid rows of this thread
+    __device__ __forceinline__ Columns(int t, int T, int N)
+    {
+        R = T / N;
+        c = t % N;
+        r0 = t / N;
+        jmax = t < N * R ? (N - r0 + R - 1) / R : 0;
+    }
+};
 
 // Per-thread partial sums of one pass over the subset, all in FP32:
 //   s[0] = sum g',  s[1] = sum g'^2,  s[2] = sum fbar g',
@@ -322,13 +390,9 @@ __global__ __launch_bounds__(T) void k_ref_nodes(RefView R, double *cache, int8_
     int parity = 0;
     const int N = R.N, h = (N - 1) / 2, n = N * N;
     const int t = threadIdx.x;
-    float dxs[P], dys[P];
-#pragma unroll
-    for (int j = 0; j < P; ++j) {
-        const int i = t + T * j;
-        dxs[j] = static_cast<float>(i % N - h);
-        dys[j] = static_cast<float>(i / N - h);
-    }
+    const Columns L(t, T, N);
+    const float dxf = static_cast<float>(L.c - h);
+    const float dy0 = static_cast<float>(L.r0 - h), dyR = static_cast<float>(L.R);
     for (int64_t node = blockIdx.x; node < R.nodes; node += gridDim.x) {
         if (flag[node] < 0) continue;
         const int xc = h + static_cast<int>(node % R.nx) * R.step;
@@ -338,9 +402,8 @@ __global__ __launch_bounds__(T) void k_ref_nodes(RefView R, double *cache, int8_
 #pragma unroll
         for (int j = 0; j < P; ++j) {
             fv[j] = gxv[j] = gyv[j] = 0.0f;
-            if (t + T * j < n) {
-                const int64_t o = static_cast<int64_t>(yc + static_cast<int>(dys[j])) * R.ppitch + xc +
-                                  static_cast<int>(dxs[j]);
+            if (j < L.jmax) {
+                const int64_t o = static_cast<int64_t>(yc - h + L.r0 + L.R * j) * R.ppitch + xc - h + L.c;
                 fv[j] = R.pf[o];
                 gxv[j] = R.pfx[o];
                 gyv[j] = R.pfy[o];
@@ -358,11 +421,12 @@ __global__ __launch_bounds__(T) void k_ref_nodes(RefView R, double *cache, int8_
         for (int i = 0; i < NV; ++i) v[i] = 0.0;
 #pragma unroll
         for (int j = 0; j < P; ++j) {
-            if (t + T * j < n) {
+            if (j < L.jmax) {
                 const float fb = fv[j] - fm32;
-                accumulate<NP>(s, fb, fb, gxv[j], gyv[j], dxs[j], dys[j]);
+                const float dyf = fmaf(static_cast<float>(j), dyR, dy0);
+                accumulate<NP>(s, fb, fb, gxv[j], gyv[j], dxf, dyf);
                 double J[NP];
-                steepest<NP>(J, gxv[j], gyv[j], dxs[j], dys[j]);
+                steepest<NP>(J, gxv[j], gyv[j], dxf, dyf);
                 int q = 3 + NP + NP;
 #pragma unroll
                 for (int a = 0; a < NP; ++a) {
@@ -783,40 +847,47 @@ __global__ __launch_bounds__(T) void k_wave(RefView R, const FrameTable frames, 
     extern __shared__ float tile[];  // ts * ts deformed coefficients
     __shared__ Acc red[2 * (T / 64) * NS];
     __shared__ int prefix[kMaxFrames + 1];
+    __shared__ int owned[kMaxFrames + 1];
     __shared__ double cache[NC];      // this subset's reference cache
     const int nframes = frames.n;
 
+    // Frame affinity: workgroups are placed on the 8 XCDs round-robin by index, so
+    // with a multiple of 8 frames the workgroups of one XCD (index mod 8) take every
+    // 8th frame and that XCD's L2 holds only those frames' coefficient windows.
+    const int G = (nframes % 8 == 0 && gridDim.x % 8 == 0) ? 8 : 1;
+    const int grp = static_cast<int>(blockIdx.x) % G;
+    const int gb = static_cast<int>(blockIdx.x) / G, gstride = static_cast<int>(gridDim.x) / G;
     const int t = threadIdx.x;
     if (t == 0) {
-        int acc = 0;
-        for (int f = 0; f < nframes; ++f) {
-            prefix[f] = acc;
+        int acc = 0, m = 0;
+        for (int f = grp; f < nframes; f += G, ++m) {
+            owned[m] = f;
+            prefix[m] = acc;
             acc += frames.f[f].counts[k];
         }
-        prefix[nframes] = acc;
+        owned[kMaxFrames] = m;
+        prefix[m] = acc;
     }
     __syncthreads();
-    const int total = __builtin_amdgcn_readfirstlane(prefix[nframes]);
-    if (static_cast<int>(blockIdx.x) >= total) return;
+    const int nown = __builtin_amdgcn_readfirstlane(owned[kMaxFrames]);
+    const int total = __builtin_amdgcn_readfirstlane(prefix[nown]);
+    if (gb >= total) return;
 
     const int N = R.N, h = (N - 1) / 2, n = N * N;
     const double inv_n = 1.0 / n;
     const int64_t nn = R.nodes;
-    float dxs[P], dys[P];
-#pragma unroll
-    for (int j = 0; j < P; ++j) {
-        const int i = t + T * j;
-        dxs[j] = static_cast<float>(i % N - h);
-        dys[j] = static_cast<float>(i / N - h);
-    }
+    const Columns L(t, T, N);
+    const float dxf = static_cast<float>(L.c - h);
+    const float dy0 = static_cast<float>(L.r0 - h), dyR = static_cast<float>(L.R);
     int parity = 0;
 
-    for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
-        int f = 0;
-        while (f + 1 < nframes && prefix[f + 1] <= gi) ++f;
-        f = __builtin_amdgcn_readfirstlane(f);
+    for (int gi = gb; gi < total; gi += gstride) {
+        int m = 0;
+        while (m + 1 < nown && prefix[m + 1] <= gi) ++m;
+        m = __builtin_amdgcn_readfirstlane(m);
+        const int f = __builtin_amdgcn_readfirstlane(owned[m]);
         const FrameState &F = frames.f[f];
-        const int li = __builtin_amdgcn_readfirstlane(gi - prefix[f]);
+        const int li = __builtin_amdgcn_readfirstlane(gi - prefix[m]);
         const int32_t *lin = (k & 1) ? F.list1 : F.list0;
         int32_t *lout = (k & 1) ? F.list0 : F.list1;
         const int node = __builtin_amdgcn_readfirstlane(lin[li]);
@@ -827,15 +898,27 @@ __global__ __launch_bounds__(T) void k_wave(RefView R, const FrameTable frames, 
         // the parent's parameters wait for the parent key
         const int8_t rf = R.flag[node];
         const uint64_t key = k > 0 ? F.pkey[node] : 0;
+        // the four possible parents' parameters are read together with the key (the key
+        // only selects one), saving a dependent round trip; indices are clamped to the grid
+        float qa[4][NP];
+        if (k > 0) {
+            const int64_t nb[4] = {static_cast<int64_t>(iy) * R.nx + max(ix - 1, 0),
+                                   static_cast<int64_t>(iy) * R.nx + min(ix + 1, R.nx - 1),
+                                   static_cast<int64_t>(max(iy - 1, 0)) * R.nx + ix,
+                                   static_cast<int64_t>(min(iy + 1, R.ny - 1)) * R.nx + ix};
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+#pragma unroll
+                for (int j = 0; j < NP; ++j) qa[d][j] = F.p[j * nn + nb[d]];
+        }
         __syncthreads();   // the previous subset is done with the LDS cache and window
         for (int q = t; q < NC; q += T) cache[q] = R.cache[static_cast<int64_t>(q) * nn + node];
         float fb[P], gx[P], gy[P];
 #pragma unroll
         for (int j = 0; j < P; ++j) {
             fb[j] = gx[j] = gy[j] = 0.0f;
-            if (t + T * j < n) {
-                const int64_t o = static_cast<int64_t>(yc + static_cast<int>(dys[j])) * R.ppitch + xc +
-                                  static_cast<int>(dxs[j]);
+            if (j < L.jmax) {
+                const int64_t o = static_cast<int64_t>(yc - h + L.r0 + L.R * j) * R.ppitch + xc - h + L.c;
                 fb[j] = R.pf[o];
                 gx[j] = R.pfx[o];
                 gy[j] = R.pfy[o];
@@ -852,13 +935,13 @@ __global__ __launch_bounds__(T) void k_wave(RefView R, const FrameTable frames, 
         } else {
             const uint32_t dir = static_cast<uint32_t>(key & 3u);
             // priority 3: parent on the left, 2: right, 1: above, 0: below
-            // (clamped: a listed node always has a key, the clamp only guards the read)
-            const int px = min(max(ix + (dir == 3 ? -1 : (dir == 2 ? 1 : 0)), 0), R.nx - 1);
-            const int py = min(max(iy + (dir == 1 ? -1 : (dir == 0 ? 1 : 0)), 0), R.ny - 1);
-            const int64_t par = static_cast<int64_t>(py) * R.nx + px;
+            const int px = ix + (dir == 3 ? -1 : (dir == 2 ? 1 : 0));
+            const int py = iy + (dir == 1 ? -1 : (dir == 0 ? 1 : 0));
+            const int sel = dir == 3 ? 0 : (dir == 2 ? 1 : (dir == 1 ? 2 : 3));
             double q[NP];
 #pragma unroll
-            for (int j = 0; j < NP; ++j) q[j] = static_cast<double>(F.p[j * nn + par]);
+            for (int j = 0; j < NP; ++j)
+                q[j] = static_cast<double>(sel == 0 ? qa[0][j] : (sel == 1 ? qa[1][j] : (sel == 2 ? qa[2][j] : qa[3][j])));
 #pragma unroll
             for (int j = 0; j < NP; ++j) p[j] = q[j];
             if (!ip.guess_copy) {
@@ -887,7 +970,7 @@ __global__ __launch_bounds__(T) void k_wave(RefView R, const FrameTable frames, 
             const float fm32 = static_cast<float>(cache[0]);
 #pragma unroll
             for (int j = 0; j < P; ++j)
-                if (t + T * j < n) fb[j] -= fm32;
+                if (j < L.jmax) fb[j] -= fm32;
             const double hd = static_cast<double>(h);
             int tox = INT_MIN / 2, toy = INT_MIN / 2;   // staged window origin (global sample coords)
 
@@ -915,8 +998,8 @@ __global__ __launch_bounds__(T) void k_wave(RefView R, const FrameTable frames, 
                         int any = 0;
 #pragma unroll
                         for (int j = 0; j < P; ++j) {
-                            if (t + T * j < n) {
-                                const double dx = dxs[j], dy = dys[j];
+                            if (j < L.jmax) {
+                                const double dx = dxf, dy = static_cast<double>(L.r0 - h + L.R * j);
                                 const double X = xc + dx + p[0] + p[2] * dx + p[3] * dy + p[6] * dx * dx +
                                                  p[7] * dx * dy + p[8] * dy * dy;
                                 const double Y = yc + dy + p[1] + p[4] * dx + p[5] * dy + p[9] * dx * dx +
@@ -1006,12 +1089,15 @@ __global__ __launch_bounds__(T) void k_wave(RefView R, const FrameTable frames, 
                 float s[NS];
 #pragma unroll
                 for (int i = 0; i < NS; ++i) s[i] = 0.0f;
+                // this thread's column: X, Y at row j are X0 + j XR, Y0 + j YR (affine part)
+                const float X0 = fmaf(A2, dy0, fmaf(A1, dxf, A0)), XR = A2 * dyR;
+                const float Y0 = fmaf(B2, dy0, fmaf(B1, dxf, B0)), YR = B2 * dyR;
 #pragma unroll
                 for (int j = 0; j < P; ++j) {
-                    if (t + T * j < n) {
-                        const float dx = dxs[j], dy = dys[j];
-                        float X = fmaf(A2, dy, fmaf(A1, dx, A0));
-                        float Y = fmaf(B2, dy, fmaf(B1, dx, B0));
+                    if (j < L.jmax) {
+                        const float dx = dxf, dy = fmaf(static_cast<float>(j), dyR, dy0);
+                        float X = fmaf(static_cast<float>(j), XR, X0);
+                        float Y = fmaf(static_cast<float>(j), YR, Y0);
                         if constexpr (NP == 12) {
                             const float xx = dx * dx, xy = dx * dy, yy = dy * dy;
                             X = fmaf(Q[2], yy, fmaf(Q[1], xy, fmaf(Q[0], xx, X)));
@@ -1159,11 +1245,14 @@ static void wave_inst(const RefView &R, const FrameTable &F, int k, bool f64, co
         k_wave<NP, T, P, false><<<grid, T, lds, s>>>(R, F, k, ip, ts, half ? 1 : 0);
 }
 
-// Pixels per thread for subset size N at T threads: the smallest supported
-// register block holding ceil(N^2 / T) pixels.
+// Rows per thread for subset size N at T threads (column-per-thread layout,
+// R = T div N rows per pass): the smallest supported register block holding
+// ceil(N / R) rows; -1 if T < N or none is large enough.
 static int pixels_per_thread(int N, int T)
 {
-    const int need = (N * N + T - 1) / T;
+    if (T < N) return -1;
+    const int R = T / N;
+    const int need = (N + R - 1) / R;
     const int opts[] = {2, 4, 8, 12, 16};
     for (int o : opts)
         if (o >= need) return o;
@@ -1211,10 +1300,9 @@ void launch_ref_nodes(const RefView &R, int np, int tps, double *cache, int8_t *
 
 bool supported_tps(int N, int tps)
 {
+    if (tps != 64 && tps != 128 && tps != 256) return false;
     const int P = pixels_per_thread(N, tps);
-    if (P < 0) return false;
-    if (tps == 64 && P < 4) return false;
-    return tps == 64 || tps == 128 || tps == 256;
+    return P > 0 && !(tps == 64 && P < 4);
 }
 
 int wave_grid_hint(int np, int tps, int device)
