@@ -91,6 +91,91 @@ def copy_probe(mib=256, reps=3):
     print(json.dumps({"copy_probe_bytes": mib * (1 << 20), "reps": reps}))
 
 
+def gigapixel(args, repeats=6, samples=24):
+    """The 32768^2 u8 pair (rigid shift + Gaussian bump, subset 41, step 20, 16
+    seeds): repeated correlations for the pair latency, and sampled parity
+    against the oracle on 256^2 crops centred on the sampled nodes."""
+    import torch
+    import oracle
+    from paper_2601_12941_amd import dic, synth
+
+    w = synth.workload("c4")
+    t0 = time.perf_counter()
+
+    def note(msg):
+        print("# %6.1f s  %s" % (time.perf_counter() - t0, msg), file=sys.stderr, flush=True)
+    X, Y, S, A = synth.draw_blobs(w.W, w.H, w.nblobs, w.sigma, w.amp, w.seed_blobs)
+    note("%d blobs drawn" % X.size)
+    field = w.field()
+    ref = synth._finish(synth._render_blobs_large(w.W, w.H, X, Y, S, A), w.noise, w.seed_noise_ref, w.bits)
+    note("reference rendered")
+    u0, v0 = field(X, Y)
+    de = synth._finish(synth._render_blobs_large(w.W, w.H, X + u0, Y + v0, S, A), w.noise, w.seed_noise_def, w.bits)
+    note("deformed rendered")
+    del X, Y, S, A, u0, v0
+    pair = synth.Pair(ref, de, synth.roi_from_field(w.W, w.H, field), field, w.bits)
+    note("roi done")
+    t_render = time.perf_counter() - t0
+    d_ref = dic.to_device_image(pair.ref)
+    d_def = dic.to_device_image(pair.deformed)
+    d_roi = torch.from_numpy(pair.roi).cuda()
+    torch.cuda.synchronize()
+    free0, total = torch.cuda.mem_get_info()
+    eng = dic.Engine(0)
+    t0 = time.perf_counter()
+    eng.set_reference(d_ref, d_roi, **w.params())
+    torch.cuda.synchronize()
+    t_ref = time.perf_counter() - t0
+    lat = []
+    out = None
+    for i in range(repeats + 1):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        out = eng.correlate(d_def, w.seeds)
+        torch.cuda.synchronize()
+        if i > 0:
+            lat.append(time.perf_counter() - t1)
+    st = eng.stats()
+    free1, _ = torch.cuda.mem_get_info()
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    # sampled parity: oracle from the ground-truth shape on a crop around the node
+    rng = np.random.default_rng(11)
+    h = (w.N - 1) // 2
+    u, v, (ux, uy, vx, vy) = synth.truth_at_nodes(pair.field, w.W, w.H, w.N, w.step)
+    cand = np.argwhere(g["status"] == 0)
+    pick = cand[rng.choice(len(cand), min(samples, len(cand)), replace=False)]
+    C = 128
+    errs, dz, used = [], [], 0
+    for j, i in pick:
+        xc, yc = h + i * w.step, h + j * w.step
+        y0, x0 = max(0, yc - C), max(0, xc - C)
+        sl = (slice(y0, min(w.H, yc + C)), slice(x0, min(w.W, xc + C)))
+        t = np.array([u[j, i], v[j, i], ux[j, i], uy[j, i], vx[j, i], vy[j, i]])
+        a = oracle.icgn(pair.ref[sl], pair.deformed[sl], xc - x0, yc - y0, t, w.N, 6, tol=w.tol, max_iter=w.max_iter)
+        b = oracle.icgn(pair.ref[sl], pair.deformed[sl], xc - x0, yc - y0, t + np.array([0.3, -0.3, 0, 0, 0, 0]),
+                        w.N, 6, tol=w.tol, max_iter=w.max_iter)
+        if a[3] != 0 or b[3] != 0 or np.abs(a[0][:2] - b[0][:2]).max() > 2e-4:
+            continue
+        used += 1
+        errs.append(max(abs(g["p"][0, j, i] - a[0][0]), abs(g["p"][1, j, i] - a[0][1])))
+        dz.append(abs(g["zncc"][j, i] - a[1]))
+    conv = (g["status"] == 0)
+    err_truth = np.hypot(g["p"][0] - u, g["p"][1] - v)[conv]
+    lat_ms = np.array(lat) * 1e3
+    rec = {"workload": "32768x32768 u8 speckle, shift (3.41, -7.92) + Gaussian bump, subset 41, step 20, 16 seeds",
+           "nodes": st["nodes"], "active": st["active"], "converged": int(conv.sum()), "waves": st["waves"],
+           "threads_per_subset": st["threads_per_subset"], "repeats": repeats,
+           "latency_ms_p50": float(np.percentile(lat_ms, 50)), "latency_ms_p99": float(np.percentile(lat_ms, 99)),
+           "converged_subsets_per_s": float(conv.sum() / np.median(lat)), "set_reference_ms": t_ref * 1e3,
+           "render_s": t_render, "sampled_parity": {"nodes": used, "max_duv_px": float(max(errs)) if errs else None,
+                                                     "max_dzncc": float(max(dz)) if dz else None},
+           "error_vs_truth_px": {"rms": float(np.sqrt((err_truth ** 2).mean())), "max": float(err_truth.max())},
+           "library_device_memory_gb": (free0 - free1) / 1e9,
+           "input_device_memory_gb": (pair.ref.nbytes + pair.deformed.nbytes + pair.roi.nbytes) / 1e9}
+    print(json.dumps(rec))
+    eng.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,11 +188,16 @@ def main():
     ap.add_argument("--tps", type=int, default=64, help="threads per subset, batched form")
     ap.add_argument("--plain-tps", type=int, default=128, help="threads per subset, plain form")
     ap.add_argument("--cpu-crop", type=int, default=2048, help="oracle sample window (0 = skip)")
+    ap.add_argument("--workload", default="2048", choices=["2048", "gigapixel"],
+                    help="2048: the 2048^2 batched/plain benchmark; gigapixel: the 32768^2 pair, repeated")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.workload == "gigapixel":
+        gigapixel(args)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)

@@ -69,6 +69,7 @@ struct dic_ctx {
     double *d_zbuf = nullptr;
     int zbuf_capacity = 0, centre_capacity = 0;
     int32_t *d_wave_total = nullptr;
+    RefView *d_view = nullptr;   // device copy of view(), read by the wave kernel
     int32_t *h_pinned = nullptr;
     hipEvent_t ev[4] = {};
     std::vector<hipEvent_t> chunk_ev;
@@ -96,6 +97,12 @@ struct dic_ctx {
         R.nx = nx;
         R.ny = ny;
         R.nodes = nodes;
+        R.max_iter = prm.max_iter;
+        R.tol2 = prm.tol * prm.tol;
+        R.zncc_min = static_cast<float>(prm.zncc_min);
+        R.guess_copy = prm.guess_mode;
+        R.half = prm.coef_fp16 != 0;
+        R.ts = tile_side(prm.subset_size);
         return R;
     }
 };
@@ -136,6 +143,7 @@ void free_reference(dic_ctx *c)
     dfree(c->ref_raw);
     dfree(c->tmp);
     dfree(c->d_wave_total);
+    dfree(c->d_view);
     for (auto &f : c->frames) {
         dfree(f.dcoef_base);
         dfree(f.pkey);
@@ -330,6 +338,8 @@ dic_status dic_set_reference(dic_ctx *c, const dic_image *ref, const uint8_t *ro
     HIPCHK(hipMemsetAsync(c->cache, 0, sizeof(double) * cache_slots(c->np) * c->nodes, s));
 
     RefView R = c->view();
+    HIPCHK(hipMalloc(&c->d_view, sizeof(RefView)));
+    HIPCHK(hipMemcpyAsync(c->d_view, &R, sizeof(RefView), hipMemcpyHostToDevice, s));
     launch_prefilter(ref->data, ref->pitch_bytes, ref->pixel, c->W, c->H, c->tmp, c->tpitch, const_cast<float *>(R.coef),
                      c->cpitch, false, s);
     launch_ref_pixels(R, c->pf, c->pfx, c->pfy, s);
@@ -441,6 +451,8 @@ dic_status dic_correlate_batch(dic_ctx *c, const dic_image *defs, int32_t nframe
         F.seed_nodes = fb.seed_nodes;
         F.nseeds = nuniq[f];
         F.stat = fb.stat;
+        F.ref = c->d_view;
+        F.k_base = 0;
         launch_prefilter(defs[f].data, defs[f].pitch_bytes, defs[f].pixel, c->W, c->H, c->tmp, c->tpitch,
                          const_cast<void *>(F.dcoef), c->cpitch, half, s);
         launch_init_frame(R, F, c->np, s);
@@ -458,12 +470,6 @@ dic_status dic_correlate_batch(dic_ctx *c, const dic_image *defs, int32_t nframe
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(c->ev[2], s));
 
-    IterParams ip;
-    ip.max_iter = c->prm.max_iter;
-    ip.tol2 = c->prm.tol * c->prm.tol;
-    ip.zncc_min = static_cast<float>(c->prm.zncc_min);
-    ip.guess_copy = c->prm.guess_mode;
-    ip.seed_radius = c->prm.seed_radius;
     const int grid = wave_grid_hint(c->np, c->tps, c->device);
     FrameTable table;
     std::memset(&table, 0, sizeof(table));
@@ -481,7 +487,7 @@ dic_status dic_correlate_batch(dic_ctx *c, const dic_image *defs, int32_t nframe
         }
         HIPCHK(hipEventRecord(c->chunk_ev[2 * nchunk], s));
         for (int j = 0; j < chunk && k <= c->nodes; ++j, ++k)
-            if (!launch_wave(R, table, k, c->np, c->tps, half, f64, ip, grid, s))
+            if (!launch_wave(table, k, c->np, c->prm.subset_size, c->tps, f64, R.ts, grid, s))
                 FAIL(DIC_E_UNSUPPORTED, "no kernel for shape %d, %d threads, subset %d", c->np, c->tps,
                      c->prm.subset_size);
         HIPCHK(hipGetLastError());

@@ -50,14 +50,13 @@ struct RefView {
     int pixel;           // dic_pixel of raw
     int W, H, N, step, nx, ny;
     int64_t nodes;
-};
-
-struct IterParams {
+    // iteration parameters of the context that owns this reference
     int max_iter;
-    double tol2;        // tol^2 (the norm is compared squared)
+    double tol2;         // tol^2 (the norm is compared squared)
     float zncc_min;
-    int guess_copy;     // 1: copy the neighbour's p, 0: extrapolate
-    int seed_radius;
+    int guess_copy;      // 1: copy the neighbour's p, 0: extrapolate
+    int half;            // deformed coefficients stored as FP16
+    int ts;              // side of the LDS coefficient window
 };
 
 // Device-resident state of one frame of a (batched) correlation.
@@ -79,6 +78,8 @@ struct FrameState {
     int32_t *seed_nodes;  // [nseeds]
     int32_t nseeds;
     unsigned long long *stat; // [0] computed, [1] converged, [2] iterations
+    const RefView *ref;   // DEVICE copy of the reference view this frame correlates against
+    int k_base;           // launch step at which this frame's wave 0 runs (wave = step - k_base)
 };
 
 // The frames of one launch, passed by value as a kernel argument: uniform
@@ -99,10 +100,11 @@ void launch_seed_search(const RefView &R, const FrameState *F_dev, int nframes, 
                         const int32_t *seed_center_dev, double *zbuf, hipStream_t s);
 void launch_seed_pick(const RefView &R, const FrameState *F_dev, int nframes, int nseeds, int radius,
                       const int32_t *seed_center_dev, const double *zbuf, hipStream_t s);
-bool launch_wave(const RefView &R, const FrameTable &F, int k, int np, int tps, bool half, bool f64,
-                 const IterParams &ip, int grid, hipStream_t s);
+bool launch_wave(const FrameTable &F, int step, int np, int N, int tps, bool f64, int max_ts, int grid,
+                 hipStream_t s);
 void launch_frame_stats(const RefView &R, const FrameState &F, hipStream_t s);
 void launch_count_wave(const FrameState *F_dev, int nframes, int k, int32_t *out, hipStream_t s);
+int pixels_per_thread(int N, int T);
 void launch_finalize(const RefView &R, const FrameState &F, int np, bool nan_unconverged, hipStream_t s);
 int wave_grid_hint(int np, int tps, int device);
 bool supported_tps(int N, int tps);

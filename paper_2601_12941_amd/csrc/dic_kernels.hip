@@ -837,8 +837,7 @@ __device__ __forceinline__ void compose_quadratic(double (&p)[12], const double 
 // One frontier wave: every subset of wave k of every frame.
 // ---------------------------------------------------------------------------
 template <int NP, int T, int P, bool F64>
-__global__ __launch_bounds__(T) void k_wave(RefView R, const FrameTable frames, int k, IterParams ip, int ts,
-                                            int half)
+__global__ __launch_bounds__(T) void k_wave(const FrameTable frames, int step)
 {
     using Acc = typename std::conditional<F64, double, float>::type;
     constexpr int NS = 3 + NP;
@@ -863,7 +862,8 @@ __global__ __launch_bounds__(T) void k_wave(RefView R, const FrameTable frames, 
         for (int f = grp; f < nframes; f += G, ++m) {
             owned[m] = f;
             prefix[m] = acc;
-            acc += frames.f[f].counts[k];
+            const int kf = step - frames.f[f].k_base;   // this frame's wave
+            acc += kf >= 0 ? frames.f[f].counts[kf] : 0;
         }
         owned[kMaxFrames] = m;
         prefix[m] = acc;
@@ -872,13 +872,6 @@ __global__ __launch_bounds__(T) void k_wave(RefView R, const FrameTable frames, 
     const int nown = __builtin_amdgcn_readfirstlane(owned[kMaxFrames]);
     const int total = __builtin_amdgcn_readfirstlane(prefix[nown]);
     if (gb >= total) return;
-
-    const int N = R.N, h = (N - 1) / 2, n = N * N;
-    const double inv_n = 1.0 / n;
-    const int64_t nn = R.nodes;
-    const Columns L(t, T, N);
-    const float dxf = static_cast<float>(L.c - h);
-    const float dy0 = static_cast<float>(L.r0 - h), dyR = static_cast<float>(L.R);
     int parity = 0;
 
     for (int gi = gb; gi < total; gi += gstride) {
@@ -887,6 +880,15 @@ __global__ __launch_bounds__(T) void k_wave(RefView R, const FrameTable frames, 
         m = __builtin_amdgcn_readfirstlane(m);
         const int f = __builtin_amdgcn_readfirstlane(owned[m]);
         const FrameState &F = frames.f[f];
+        const RefView R = *F.ref;                 // this frame's reference (uniform loads)
+        const int k = step - F.k_base;            // this frame's wave
+        const int ts = R.ts, half = R.half;
+        const int N = R.N, h = (N - 1) / 2, n = N * N;
+        const double inv_n = 1.0 / n;
+        const int64_t nn = R.nodes;
+        const Columns L(t, T, N);
+        const float dxf = static_cast<float>(L.c - h);
+        const float dy0 = static_cast<float>(L.r0 - h), dyR = static_cast<float>(L.R);
         const int li = __builtin_amdgcn_readfirstlane(gi - prefix[m]);
         const int32_t *lin = (k & 1) ? F.list1 : F.list0;
         int32_t *lout = (k & 1) ? F.list0 : F.list1;
@@ -944,7 +946,7 @@ __global__ __launch_bounds__(T) void k_wave(RefView R, const FrameTable frames, 
                 q[j] = static_cast<double>(sel == 0 ? qa[0][j] : (sel == 1 ? qa[1][j] : (sel == 2 ? qa[2][j] : qa[3][j])));
 #pragma unroll
             for (int j = 0; j < NP; ++j) p[j] = q[j];
-            if (!ip.guess_copy) {
+            if (!R.guess_copy) {
                 const double ex = static_cast<double>((ix - px) * R.step);
                 const double ey = static_cast<double>((iy - py) * R.step);
                 p[0] = q[0] + q[2] * ex + q[3] * ey;
@@ -974,7 +976,7 @@ __global__ __launch_bounds__(T) void k_wave(RefView R, const FrameTable frames, 
             const double hd = static_cast<double>(h);
             int tox = INT_MIN / 2, toy = INT_MIN / 2;   // staged window origin (global sample coords)
 
-            for (int it = 1; it <= ip.max_iter; ++it) {
+            for (int it = 1; it <= R.max_iter; ++it) {
                 iters = it;
                 // ---- bounding box of the warped subset (exact for affine: its corners)
                 double xmin, xmax, ymin, ymax;
@@ -1184,8 +1186,8 @@ __global__ __launch_bounds__(T) void k_wave(RefView R, const FrameTable frames, 
 #pragma unroll
                 for (int a = 0; a < NP; ++a) bad = bad || isnan(p[a]);
                 if (bad) { status = kNan; break; }
-                if (nrm < ip.tol2) {
-                    status = zncc_out >= ip.zncc_min ? kConverged : kLowZncc;
+                if (nrm < R.tol2) {
+                    status = zncc_out >= R.zncc_min ? kConverged : kLowZncc;
                     break;
                 }
             }
@@ -1235,20 +1237,19 @@ __global__ __launch_bounds__(T) void k_wave(RefView R, const FrameTable frames, 
 // dispatch
 // ---------------------------------------------------------------------------
 template <int NP, int T, int P>
-static void wave_inst(const RefView &R, const FrameTable &F, int k, bool f64, const IterParams &ip, int ts, bool half,
-                      int grid, hipStream_t s)
+static void wave_inst(const FrameTable &F, int step, bool f64, int max_ts, int grid, hipStream_t s)
 {
-    const size_t lds = static_cast<size_t>(ts) * ts * sizeof(float);
+    const size_t lds = static_cast<size_t>(max_ts) * max_ts * sizeof(float);
     if (f64)
-        k_wave<NP, T, P, true><<<grid, T, lds, s>>>(R, F, k, ip, ts, half ? 1 : 0);
+        k_wave<NP, T, P, true><<<grid, T, lds, s>>>(F, step);
     else
-        k_wave<NP, T, P, false><<<grid, T, lds, s>>>(R, F, k, ip, ts, half ? 1 : 0);
+        k_wave<NP, T, P, false><<<grid, T, lds, s>>>(F, step);
 }
 
 // Rows per thread for subset size N at T threads (column-per-thread layout,
 // R = T div N rows per pass): the smallest supported register block holding
 // ceil(N / R) rows; -1 if T < N or none is large enough.
-static int pixels_per_thread(int N, int T)
+int pixels_per_thread(int N, int T)
 {
     if (T < N) return -1;
     const int R = T / N;
@@ -1269,14 +1270,17 @@ int tile_side(int N)
     return ((N + 17 + 15) / 16) * 16;
 }
 
-bool launch_wave(const RefView &R, const FrameTable &F, int k, int np, int tps, bool half, bool f64,
-                 const IterParams &ip, int grid, hipStream_t s)
+// One launch for every frame of F at launch step `step`.  All frames must use the
+// same shape and threads per subset, and subset sizes whose rows fit the register
+// block chosen for N (the largest subset of the launch); the LDS window is sized
+// for the largest frame's window side.
+bool launch_wave(const FrameTable &F, int step, int np, int N, int tps, bool f64, int max_ts, int grid,
+                 hipStream_t s)
 {
-    const int P = pixels_per_thread(R.N, tps);
-    const int ts = tile_side(R.N);
+    const int P = pixels_per_thread(N, tps);
 #define X(NP_, T_, P_)                                                                                                \
     if (np == NP_ && tps == T_ && P == P_) {                                                                          \
-        wave_inst<NP_, T_, P_>(R, F, k, f64, ip, ts, half, grid, s);                                      \
+        wave_inst<NP_, T_, P_>(F, step, f64, max_ts, grid, s);                                      \
         return true;                                                                                                   \
     }
     DIC_TP_CASES(6, X)

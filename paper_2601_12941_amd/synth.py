@@ -18,8 +18,11 @@ each image's noise uses its own generator.
 """
 from __future__ import annotations
 
+import ctypes
 import dataclasses
 import math
+import os
+import subprocess
 from typing import Callable, Optional
 
 import numpy as np
@@ -65,7 +68,41 @@ def _render_blobs(W: int, H: int, X, Y, S, A, chunk_px: int = 1 << 23) -> np.nda
     return img.reshape(H, W)
 
 
+_LARGE = 1 << 24          # pixels above which the C renderer and chunked finishing are used
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _speckle_lib():
+    """Compile (if needed) and load the OpenMP blob renderer used for large images."""
+    src = os.path.join(_HERE, "speckle_render.c")
+    lib = os.path.join(_HERE, "libspeckle.so")
+    if not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
+        tmp = lib + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-o", tmp, src, "-lm"])
+        os.replace(tmp, lib)
+    L = ctypes.CDLL(lib)
+    dp = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+    L.speckle_render.argtypes = [np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS"), ctypes.c_long,
+                                 ctypes.c_long, dp, dp, dp, dp, np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS"),
+                                 ctypes.c_long, ctypes.c_double, ctypes.c_long]
+    return L
+
+
+def _render_blobs_large(W: int, H: int, X, Y, S, A) -> np.ndarray:
+    """Same blob model as _render_blobs, float32 output, band-parallel in C."""
+    X = np.ascontiguousarray(X, np.float64)
+    Y = np.ascontiguousarray(Y, np.float64)
+    S = np.ascontiguousarray(S, np.float64)
+    A = np.ascontiguousarray(A, np.float64)
+    order = np.argsort(Y, kind="stable").astype(np.int64)
+    img = np.empty((H, W), np.float32)
+    _speckle_lib().speckle_render(img, W, H, X, Y, S, A, order, X.size, float(S.max()) if X.size else 0.0, 256)
+    return img
+
+
 def _finish(img: np.ndarray, noise_sigma: float, noise_seed: Optional[int], bits: Optional[int]):
+    if img.size > _LARGE:
+        return _finish_chunked(img, noise_sigma, noise_seed, bits)
     out = img.copy()
     if noise_sigma > 0 and noise_seed is not None:
         rng = np.random.Generator(np.random.PCG64(noise_seed))
@@ -74,6 +111,24 @@ def _finish(img: np.ndarray, noise_sigma: float, noise_seed: Optional[int], bits
         return out.astype(np.float32)
     out = np.clip(np.rint(out), 0, (1 << bits) - 1)
     return out.astype(np.uint8 if bits <= 8 else np.uint16)
+
+
+def _finish_chunked(img: np.ndarray, noise_sigma, noise_seed, bits, rows=2048):
+    """Row-chunked noise, rounding and clipping (the noise values are the same
+    sequence a single draw would give)."""
+    H, W = img.shape
+    dt = np.float32 if bits is None else (np.uint8 if bits <= 8 else np.uint16)
+    out = np.empty((H, W), dt)
+    rng = np.random.Generator(np.random.PCG64(noise_seed)) if noise_sigma > 0 and noise_seed is not None else None
+    for y0 in range(0, H, rows):
+        blk = img[y0:y0 + rows].astype(np.float64)
+        if rng is not None:
+            blk += rng.normal(0.0, noise_sigma, size=blk.shape)
+        if bits is None:
+            out[y0:y0 + rows] = blk
+        else:
+            out[y0:y0 + rows] = np.clip(np.rint(blk), 0, (1 << bits) - 1)
+    return out
 
 
 # --------------------------------------------------------------------------
@@ -175,22 +230,29 @@ def draw_blobs(W, H, nblobs, sigma, amp, seed):
     return X, Y, S, A
 
 
-def roi_from_field(W: int, H: int, field: Field, margin: int = 4) -> np.ndarray:
+def roi_from_field(W: int, H: int, field: Field, margin: int = 4, rows: int = 1024) -> np.ndarray:
     """Pixels >= margin inside the image whose displaced position is also >= margin inside."""
-    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
-    u, v = field(xx, yy)
+    out = np.empty((H, W), np.uint8)
     lo = margin
-    ok = (xx >= lo) & (xx <= W - 1 - lo) & (yy >= lo) & (yy <= H - 1 - lo)
-    ok &= (xx + u >= lo) & (xx + u <= W - 1 - lo) & (yy + v >= lo) & (yy + v <= H - 1 - lo)
-    return ok.astype(np.uint8)
+    xx = np.arange(W, dtype=np.float64)[None, :]
+    for y0 in range(0, H, rows):
+        yy = np.arange(y0, min(H, y0 + rows), dtype=np.float64)[:, None]
+        X = np.broadcast_to(xx, (yy.shape[0], W))
+        Y = np.broadcast_to(yy, (yy.shape[0], W))
+        u, v = field(X, Y)
+        ok = (X >= lo) & (X <= W - 1 - lo) & (Y >= lo) & (Y <= H - 1 - lo)
+        ok &= (X + u >= lo) & (X + u <= W - 1 - lo) & (Y + v >= lo) & (Y + v <= H - 1 - lo)
+        out[y0:y0 + yy.shape[0]] = ok
+    return out
 
 
 def make_pair(W, H, nblobs, sigma, amp, field: Field, noise_sigma, bits, seed_blobs,
               seed_noise_ref, seed_noise_def, roi_margin=4) -> Pair:
     X, Y, S, A = draw_blobs(W, H, nblobs, sigma, amp, seed_blobs)
-    ref = _render_blobs(W, H, X, Y, S, A)
+    render = _render_blobs_large if W * H > _LARGE else _render_blobs
+    ref = render(W, H, X, Y, S, A)
     u, v = field(X, Y)
-    de = _render_blobs(W, H, X + u, Y + v, S, A)
+    de = render(W, H, X + u, Y + v, S, A)
     return Pair(_finish(ref, noise_sigma, seed_noise_ref, bits),
                 _finish(de, noise_sigma, seed_noise_def, bits),
                 roi_from_field(W, H, field, roi_margin), field, bits)
