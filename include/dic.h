@@ -174,6 +174,63 @@ dic_status dic_destroy(dic_ctx *c);
 /* Message of the last error on this context ("" if none); valid until the next call. */
 const char *dic_last_error(const dic_ctx *c);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of correlation requests.
+ *
+ * A server keeps reference precomputes resident (dic_server_add_reference,
+ * one per reference image, region and parameter set) and runs requests (one
+ * deformed frame against one resident reference each).  Submitted requests
+ * wait in FIFO order; at every dic_server_step call the server admits waiting
+ * requests while an active slot is free and their scratch fits the HBM budget,
+ * then advances every active request by one frontier wave per launch step:
+ * all active requests with the same shape and threads per subset share one
+ * launch per step, each at its own wave.  Requests whose propagation has ended
+ * are retired (results final, scratch returned to the pool) at the end of the
+ * call.  A request's results are the ones dic_correlate gives for it alone.
+ * Results arrays are caller-owned DEVICE memory, as for dic_correlate, and
+ * must stay allocated until the request is done.
+ * ------------------------------------------------------------------------ */
+typedef struct dic_server dic_server;
+
+typedef struct {
+    int32_t max_active;       /* requests on the device at once, 1..64 */
+    double hbm_budget_bytes;  /* device bytes for resident references plus active requests' scratch */
+} dic_server_params;
+
+typedef struct {
+    int64_t submitted, admitted, completed;
+    int32_t active, waiting;
+    int64_t steps;            /* launch steps so far */
+    double used_bytes;        /* references + active requests */
+    double pool_bytes;        /* request scratch kept for reuse */
+} dic_server_stats;
+
+dic_status dic_server_create(dic_server **out, int device, void *hip_stream, const dic_server_params *prm);
+
+/* Make a reference resident (same arguments as dic_set_reference); *ref_id
+ * names it in later submissions.  Fails with DIC_E_NOMEM beyond the budget. */
+dic_status dic_server_add_reference(dic_server *s, const dic_image *ref, const uint8_t *roi_mask_dev,
+                                    const dic_params *prm, int32_t *ref_id);
+
+/* Queue a request: deformed image (DEVICE, same size as the reference),
+ * host seeds, caller-allocated DEVICE results.  *ticket identifies it.  The
+ * image and result arrays must stay valid until the request is done. */
+dic_status dic_server_submit(dic_server *s, int32_t ref_id, const dic_image *def, const dic_seed *seeds,
+                             int32_t nseeds, dic_result *out, int64_t *ticket);
+
+/* Admit what fits, run `steps` launch steps (1..256), retire finished
+ * requests.  Returns after the device work of the call has completed. */
+dic_status dic_server_step(dic_server *s, int32_t steps);
+
+/* *done = 1 once the request's results are final; *status is then DIC_OK or
+ * the request's error (DIC_E_NOSEED, DIC_E_NOMEM if it can never fit).  st
+ * (may be NULL) receives the request's counters. */
+dic_status dic_server_poll(dic_server *s, int64_t ticket, int32_t *done, int32_t *status, dic_stats *st);
+
+dic_status dic_server_get_stats(const dic_server *s, dic_server_stats *out);
+dic_status dic_server_destroy(dic_server *s);
+const char *dic_server_last_error(const dic_server *s);
+
 #ifdef __cplusplus
 }
 #endif

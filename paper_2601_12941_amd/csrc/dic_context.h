@@ -1,0 +1,205 @@
+// Internal: the library context and the helpers shared by the engine
+// (dic_engine.hip) and the serving loop (dic_server.hip).  Not public ABI.
+#pragma once
+
+#include "../../include/dic.h"
+#include "dic_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace dicmi {
+
+struct FrameBuf {
+    void *dcoef_base = nullptr;  // padded deformed coefficients
+    uint64_t *pkey = nullptr;
+    int32_t *list0 = nullptr, *list1 = nullptr, *counts = nullptr;
+    double *seed_p = nullptr;
+    int32_t *seed_nodes = nullptr;
+    unsigned long long *stat = nullptr;
+};
+
+inline size_t pixel_size(int pixel) { return pixel == DIC_PIX_U8 ? 1 : (pixel == DIC_PIX_U16 ? 2 : 4); }
+
+inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+} // namespace dicmi
+
+using namespace dicmi;
+
+struct dic_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    bool has_ref = false;
+    dic_params prm{};
+    int W = 0, H = 0, nx = 0, ny = 0, np = 6, tps = 64;
+    int64_t nodes = 0, active = 0;
+    int ref_pixel = 0;
+
+    float *ref_coef_base = nullptr;
+    int64_t cpitch = 0;            // coefficient row pitch (elements)
+    float *pf = nullptr, *pfx = nullptr, *pfy = nullptr;
+    int64_t ppitch = 0;
+    double *cache = nullptr;
+    int8_t *flag = nullptr;
+    void *ref_raw = nullptr;
+    float *tmp = nullptr;          // prefilter row-pass scratch
+    int64_t tpitch = 0;
+    std::vector<int8_t> flag_host;
+
+    std::vector<FrameBuf> frames;
+    FrameState *d_frames = nullptr;
+    std::vector<FrameState> h_frames;
+    int32_t *d_centre = nullptr;
+    double *d_zbuf = nullptr;
+    int zbuf_capacity = 0, centre_capacity = 0;
+    int32_t *d_wave_total = nullptr;
+    RefView *d_view = nullptr;   // device copy of view(), read by the wave kernel
+    int32_t *h_pinned = nullptr;
+    hipEvent_t ev[4] = {};
+    std::vector<hipEvent_t> chunk_ev;
+    dic_stats stats{};
+
+    size_t coef_elems() const { return static_cast<size_t>(cpitch) * (H + 2 * kPad); }
+
+    RefView view() const
+    {
+        RefView R;
+        R.coef = ref_coef_base + kPad * cpitch + kPad;
+        R.cpitch = cpitch;
+        R.pf = pf;
+        R.pfx = pfx;
+        R.pfy = pfy;
+        R.ppitch = ppitch;
+        R.cache = cache;
+        R.flag = flag;
+        R.raw = ref_raw;
+        R.pixel = ref_pixel;
+        R.W = W;
+        R.H = H;
+        R.N = prm.subset_size;
+        R.step = prm.step;
+        R.nx = nx;
+        R.ny = ny;
+        R.nodes = nodes;
+        R.max_iter = prm.max_iter;
+        R.tol2 = prm.tol * prm.tol;
+        R.zncc_min = static_cast<float>(prm.zncc_min);
+        R.guess_copy = prm.guess_mode;
+        R.half = prm.coef_fp16 != 0;
+        R.ts = tile_side(prm.subset_size);
+        return R;
+    }
+};
+
+#define FAIL(code, ...)                                                                                               \
+    do {                                                                                                              \
+        char buf_[512];                                                                                               \
+        snprintf(buf_, sizeof(buf_), __VA_ARGS__);                                                                    \
+        c->err = buf_;                                                                                                \
+        return code;                                                                                                  \
+    } while (0)
+
+#define HIPCHK(expr)                                                                                                  \
+    do {                                                                                                              \
+        hipError_t e_ = (expr);                                                                                       \
+        if (e_ != hipSuccess) {                                                                                       \
+            if (e_ == hipErrorOutOfMemory) FAIL(DIC_E_NOMEM, "%s: %s", #expr, hipGetErrorString(e_));               \
+            FAIL(DIC_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));                                              \
+        }                                                                                                             \
+    } while (0)
+
+namespace dicmi {
+
+template <typename T> inline void dfree(T *&p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+inline void free_reference(dic_ctx *c)
+{
+    dfree(c->ref_coef_base);
+    dfree(c->pf);
+    dfree(c->pfx);
+    dfree(c->pfy);
+    dfree(c->cache);
+    dfree(c->flag);
+    dfree(c->ref_raw);
+    dfree(c->tmp);
+    dfree(c->d_wave_total);
+    dfree(c->d_view);
+    for (auto &f : c->frames) {
+        dfree(f.dcoef_base);
+        dfree(f.pkey);
+        dfree(f.list0);
+        dfree(f.list1);
+        dfree(f.counts);
+        dfree(f.seed_p);
+        dfree(f.seed_nodes);
+        dfree(f.stat);
+    }
+    c->frames.clear();
+    c->has_ref = false;
+}
+
+inline dic_status check_image(dic_ctx *c, const dic_image *im, const char *what)
+{
+    if (!im) FAIL(DIC_E_INVAL, "%s image is NULL", what);
+    if (!im->data) FAIL(DIC_E_INVAL, "%s image data is NULL", what);
+    if (im->pixel < DIC_PIX_U8 || im->pixel > DIC_PIX_F32) FAIL(DIC_E_INVAL, "%s pixel type %d", what, im->pixel);
+    if (im->width < 1 || im->height < 1) FAIL(DIC_E_INVAL, "%s size %dx%d", what, im->width, im->height);
+    if (im->pitch_bytes < static_cast<int64_t>(im->width * pixel_size(im->pixel)))
+        FAIL(DIC_E_INVAL, "%s pitch %lld below row size", what, static_cast<long long>(im->pitch_bytes));
+    return DIC_OK;
+}
+
+// Ensure per-frame scratch for `n` frames.
+inline dic_status ensure_frames(dic_ctx *c, int n)
+{
+    const int np = c->np;
+    const bool half = c->prm.coef_fp16 != 0;
+    while (static_cast<int>(c->frames.size()) < n) {
+        FrameBuf f;
+        HIPCHK(hipMalloc(&f.dcoef_base, c->coef_elems() * (half ? sizeof(__half) : sizeof(float))));
+        HIPCHK(hipMalloc(&f.pkey, sizeof(uint64_t) * c->nodes));
+        HIPCHK(hipMalloc(&f.list0, sizeof(int32_t) * c->nodes));
+        HIPCHK(hipMalloc(&f.list1, sizeof(int32_t) * c->nodes));
+        HIPCHK(hipMalloc(&f.counts, sizeof(int32_t) * (c->nodes + 2)));
+        HIPCHK(hipMalloc(&f.stat, sizeof(unsigned long long) * 4));
+        f.seed_p = nullptr;
+        f.seed_nodes = nullptr;
+        c->frames.push_back(f);
+    }
+    (void)np;
+    if (!c->d_frames) HIPCHK(hipMalloc(&c->d_frames, sizeof(FrameState) * kMaxFrames));
+    return DIC_OK;
+}
+
+// Nearest active node to (x, y), ties to smaller y then smaller x; -1 if none.
+inline int64_t snap_seed(const dic_ctx *c, double x, double y)
+{
+    const int h = (c->prm.subset_size - 1) / 2, s = c->prm.step;
+    int64_t best = -1;
+    double bd = 0.0;
+    for (int j = 0; j < c->ny; ++j)
+        for (int i = 0; i < c->nx; ++i) {
+            const int64_t node = static_cast<int64_t>(j) * c->nx + i;
+            if (c->flag_host[node] < 0) continue;
+            const double dx = h + i * s - x, dy = h + j * s - y;
+            const double d = dx * dx + dy * dy;
+            if (best < 0 || d < bd) {
+                best = node;
+                bd = d;
+            }
+        }
+    return best;
+}
+
+} // namespace dicmi

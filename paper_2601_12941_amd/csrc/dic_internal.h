@@ -80,6 +80,7 @@ struct FrameState {
     unsigned long long *stat; // [0] computed, [1] converged, [2] iterations
     const RefView *ref;   // DEVICE copy of the reference view this frame correlates against
     int k_base;           // launch step at which this frame's wave 0 runs (wave = step - k_base)
+    int kmax;             // last valid index of counts (nodes + 1)
 };
 
 // The frames of one launch, passed by value as a kernel argument: uniform
@@ -102,6 +103,7 @@ void launch_seed_pick(const RefView &R, const FrameState *F_dev, int nframes, in
                       const int32_t *seed_center_dev, const double *zbuf, hipStream_t s);
 bool launch_wave(const FrameTable &F, int step, int np, int N, int tps, bool f64, int max_ts, int grid,
                  hipStream_t s);
+void launch_gather_next(const FrameState *F_dev, int n, int step, int32_t *out, hipStream_t s);
 void launch_frame_stats(const RefView &R, const FrameState &F, hipStream_t s);
 void launch_count_wave(const FrameState *F_dev, int nframes, int k, int32_t *out, hipStream_t s);
 int pixels_per_thread(int N, int T);

@@ -718,6 +718,21 @@ void launch_frame_stats(const RefView &R, const FrameState &F, hipStream_t s)
     k_frame_stats<<<static_cast<unsigned>(blocks), 256, 0, s>>>(R, F);
 }
 
+// For each of n frames (device array), the size of the wave it runs at launch step
+// `step` (0 before its start or past its counts).
+__global__ void k_gather_next(const FrameState *frames, int n, int step, int32_t *out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int kf = step - frames[i].k_base;
+    out[i] = (kf >= 0 && kf <= frames[i].kmax) ? frames[i].counts[kf] : 0;
+}
+
+void launch_gather_next(const FrameState *F_dev, int n, int step, int32_t *out, hipStream_t s)
+{
+    if (n > 0) k_gather_next<<<(n + 63) / 64, 64, 0, s>>>(F_dev, n, step, out);
+}
+
 // Size of wave k summed over the frames (read by the host once per chunk).
 __global__ void k_count_wave(const FrameState *frames, int nframes, int k, int32_t *out)
 {
@@ -863,7 +878,7 @@ __global__ __launch_bounds__(T) void k_wave(const FrameTable frames, int step)
             owned[m] = f;
             prefix[m] = acc;
             const int kf = step - frames.f[f].k_base;   // this frame's wave
-            acc += kf >= 0 ? frames.f[f].counts[kf] : 0;
+            acc += (kf >= 0 && kf <= frames.f[f].kmax) ? frames.f[f].counts[kf] : 0;
         }
         owned[kMaxFrames] = m;
         prefix[m] = acc;

@@ -4,7 +4,8 @@ Argument marshalling only: every step of the correlation runs in the HIP
 library.  PyTorch supplies device memory and the stream.  The entry points
 keep the C names (dic_create, dic_set_reference, dic_grid_shape,
 dic_correlate, dic_correlate_batch, dic_get_stats, dic_destroy,
-dic_last_error); `Engine` wraps them for torch tensors.
+dic_last_error, and the dic_server_* serving calls); `Engine` and `Server`
+wrap them for torch tensors.
 
 There is no fallback: if the library is missing or cannot be loaded, every
 call raises.
@@ -28,7 +29,9 @@ NODE = dict(CONVERGED=0, NOT_REACHED=1, NOT_IN_ROI=2, MAX_ITER=3, LOW_ZNCC=4, OU
 
 # exported names, in the order include/dic.h declares them
 EXPORTS = ["dic_create", "dic_set_reference", "dic_grid_shape", "dic_correlate", "dic_correlate_batch",
-           "dic_get_stats", "dic_destroy", "dic_last_error"]
+           "dic_get_stats", "dic_destroy", "dic_last_error",
+           "dic_server_create", "dic_server_add_reference", "dic_server_submit", "dic_server_step",
+           "dic_server_poll", "dic_server_get_stats", "dic_server_destroy", "dic_server_last_error"]
 
 
 class DicImage(C.Structure):
@@ -60,6 +63,16 @@ class DicStats(C.Structure):
                 ("ms_wave_kernels", C.c_double), ("wave_launches", C.c_int32)]
 
 
+class DicServerParams(C.Structure):
+    _fields_ = [("max_active", C.c_int32), ("hbm_budget_bytes", C.c_double)]
+
+
+class DicServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
+                ("active", C.c_int32), ("waiting", C.c_int32), ("steps", C.c_int64), ("used_bytes", C.c_double),
+                ("pool_bytes", C.c_double)]
+
+
 _lib = None
 
 
@@ -81,8 +94,18 @@ def load_library(path: str = LIB_PATH):
     L.dic_destroy.argtypes = [C.c_void_p]
     L.dic_last_error.argtypes = [C.c_void_p]
     L.dic_last_error.restype = C.c_char_p
+    L.dic_server_create.argtypes = [P(C.c_void_p), C.c_int, C.c_void_p, P(DicServerParams)]
+    L.dic_server_add_reference.argtypes = [C.c_void_p, P(DicImage), C.c_void_p, P(DicParams), P(C.c_int32)]
+    L.dic_server_submit.argtypes = [C.c_void_p, C.c_int32, P(DicImage), P(DicSeed), C.c_int32, P(DicResult),
+                                    P(C.c_int64)]
+    L.dic_server_step.argtypes = [C.c_void_p, C.c_int32]
+    L.dic_server_poll.argtypes = [C.c_void_p, C.c_int64, P(C.c_int32), P(C.c_int32), P(DicStats)]
+    L.dic_server_get_stats.argtypes = [C.c_void_p, P(DicServerStats)]
+    L.dic_server_destroy.argtypes = [C.c_void_p]
+    L.dic_server_last_error.argtypes = [C.c_void_p]
+    L.dic_server_last_error.restype = C.c_char_p
     for n in EXPORTS:
-        if n != "dic_last_error":
+        if not n.endswith("last_error"):
             getattr(L, n).restype = C.c_int
     _lib = L
     return L
@@ -144,6 +167,60 @@ def dic_get_stats(ctx) -> dict:
 
 def dic_destroy(ctx):
     load_library().dic_destroy(ctx)
+
+
+def dic_server_create(device: int, stream: Optional[int], max_active: int, hbm_budget_bytes: float) -> C.c_void_p:
+    srv = C.c_void_p()
+    prm = DicServerParams(int(max_active), float(hbm_budget_bytes))
+    rc = load_library().dic_server_create(C.byref(srv), int(device), C.c_void_p(stream or 0), C.byref(prm))
+    if rc != DIC_OK:
+        raise DicError(rc, "dic_server_create failed")
+    return srv
+
+
+def dic_server_last_error(srv) -> str:
+    m = load_library().dic_server_last_error(srv)
+    return m.decode() if m else ""
+
+
+def _scheck(srv, rc):
+    if rc != DIC_OK:
+        raise DicError(rc, dic_server_last_error(srv))
+
+
+def dic_server_add_reference(srv, image: DicImage, roi_ptr: int, params: DicParams) -> int:
+    rid = C.c_int32()
+    _scheck(srv, load_library().dic_server_add_reference(srv, C.byref(image), C.c_void_p(roi_ptr or 0),
+                                                         C.byref(params), C.byref(rid)))
+    return rid.value
+
+
+def dic_server_submit(srv, ref_id: int, image: DicImage, seeds: Sequence[DicSeed], result: DicResult) -> int:
+    arr = (DicSeed * len(seeds))(*seeds)
+    t = C.c_int64()
+    _scheck(srv, load_library().dic_server_submit(srv, int(ref_id), C.byref(image), arr, len(seeds),
+                                                  C.byref(result), C.byref(t)))
+    return t.value
+
+
+def dic_server_step(srv, steps: int = 1):
+    _scheck(srv, load_library().dic_server_step(srv, int(steps)))
+
+
+def dic_server_poll(srv, ticket: int):
+    done, status, st = C.c_int32(), C.c_int32(), DicStats()
+    _scheck(srv, load_library().dic_server_poll(srv, int(ticket), C.byref(done), C.byref(status), C.byref(st)))
+    return bool(done.value), status.value, {k: getattr(st, k) for k, _ in DicStats._fields_}
+
+
+def dic_server_get_stats(srv) -> dict:
+    s = DicServerStats()
+    _scheck(srv, load_library().dic_server_get_stats(srv, C.byref(s)))
+    return {k: getattr(s, k) for k, _ in DicServerStats._fields_}
+
+
+def dic_server_destroy(srv):
+    load_library().dic_server_destroy(srv)
 
 
 # ---- torch convenience -----------------------------------------------------
@@ -256,3 +333,92 @@ class Engine:
 
     def stats(self) -> dict:
         return dic_get_stats(self.ctx)
+
+
+def _params(subset_size, step, shape=6, tol=1e-4, max_iter=50, zncc_min=0.7, seed_radius=8, guess="extrapolate",
+            coef_fp16=False, reduce_fp64=True, nan_unconverged=False, threads_per_subset=0) -> DicParams:
+    return DicParams(subset_size, step, shape, max_iter, tol, zncc_min, seed_radius, 1 if guess == "copy" else 0,
+                     int(bool(coef_fp16)), int(bool(reduce_fp64)), int(bool(nan_unconverged)), threads_per_subset)
+
+
+def _roi_ptr(roi, ref) -> int:
+    if roi is None:
+        return 0
+    import torch
+    if roi.dtype != torch.uint8 or not roi.is_cuda or not roi.is_contiguous() or tuple(roi.shape) != tuple(ref.shape):
+        raise ValueError("roi must be a contiguous uint8 device tensor shaped like the image")
+    return roi.data_ptr()
+
+
+def _grid(subset_size, step, W, H):
+    """Node grid of a reference (the same rule as dic_grid_shape)."""
+    return (W - subset_size) // step + 1, (H - subset_size) // step + 1
+
+
+class Server:
+    """Continuous-batching server on one device and the current torch stream.
+
+    add_reference() makes a reference resident; submit() queues a request and
+    returns (ticket, output tensors); step() admits and advances requests;
+    poll() tells whether a ticket is done.  Deformed images and outputs are
+    kept alive here until their request is done.
+    """
+
+    def __init__(self, device: int = 0, max_active: int = 16, hbm_budget_bytes: float = 64e9):
+        import torch
+        self.device = torch.device("cuda", device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.srv = dic_server_create(device, self.stream.cuda_stream, max_active, hbm_budget_bytes)
+        self._refs = {}
+        self._live = {}
+
+    def close(self):
+        if self.srv is not None:
+            dic_server_destroy(self.srv)
+            self.srv = None
+            self._live.clear()
+            self._refs.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_reference(self, ref, roi=None, **params) -> int:
+        prm = _params(**params)
+        rid = dic_server_add_reference(self.srv, _image(ref), _roi_ptr(roi, ref), prm)
+        nx, ny = _grid(prm.subset_size, prm.step, ref.shape[1], ref.shape[0])
+        self._refs[rid] = (ref, roi, prm.shape, nx, ny)
+        return rid
+
+    def submit(self, ref_id: int, deformed, seeds):
+        import torch
+        if ref_id not in self._refs:   # the library reports the unknown id
+            dic_server_submit(self.srv, ref_id, _image(deformed), Engine._seeds(seeds), DicResult())
+            raise DicError(DIC_E_INVAL, "unknown reference %d" % ref_id)
+        _, _, shape, nx, ny = self._refs[ref_id]
+        d = self.device
+        out = dict(p=torch.empty((shape, ny, nx), dtype=torch.float32, device=d),
+                   zncc=torch.empty((ny, nx), dtype=torch.float32, device=d),
+                   iters=torch.empty((ny, nx), dtype=torch.int16, device=d),
+                   status=torch.empty((ny, nx), dtype=torch.int8, device=d),
+                   wave=torch.empty((ny, nx), dtype=torch.int32, device=d))
+        res = DicResult(out["p"].data_ptr(), out["zncc"].data_ptr(), out["iters"].data_ptr(),
+                        out["status"].data_ptr(), out["wave"].data_ptr())
+        t = dic_server_submit(self.srv, ref_id, _image(deformed), Engine._seeds(seeds), res)
+        self._live[t] = (deformed, out)
+        return t, out
+
+    def step(self, steps: int = 1):
+        dic_server_step(self.srv, steps)
+
+    def poll(self, ticket: int):
+        """(done, status code, counters); a done ticket's tensors are released here."""
+        done, status, st = dic_server_poll(self.srv, ticket)
+        if done:
+            self._live.pop(ticket, None)
+        return done, status, st
+
+    def stats(self) -> dict:
+        return dic_server_get_stats(self.srv)

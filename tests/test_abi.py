@@ -54,6 +54,12 @@ int main(void) {
   F(dic_result, p) F(dic_result, zncc) F(dic_result, iters) F(dic_result, status) F(dic_result, wave)
   printf("dic_stats %zu\n", sizeof(dic_stats));
   F(dic_stats, waves) F(dic_stats, ms_total) F(dic_stats, ms_wave_kernels) F(dic_stats, wave_launches)
+  printf("dic_server_params %zu\n", sizeof(dic_server_params));
+  F(dic_server_params, max_active) F(dic_server_params, hbm_budget_bytes)
+  printf("dic_server_stats %zu\n", sizeof(dic_server_stats));
+  F(dic_server_stats, submitted) F(dic_server_stats, admitted) F(dic_server_stats, completed)
+  F(dic_server_stats, active) F(dic_server_stats, waiting) F(dic_server_stats, steps)
+  F(dic_server_stats, used_bytes) F(dic_server_stats, pool_bytes)
   return 0;
 }
 """
@@ -69,7 +75,8 @@ int main(void) {
 def test_struct_layouts_match_header():
     lay = {k: int(v) for k, v in _c_layout().items()}
     for name, cls in (("dic_image", dic.DicImage), ("dic_params", dic.DicParams), ("dic_seed", dic.DicSeed),
-                      ("dic_result", dic.DicResult), ("dic_stats", dic.DicStats)):
+                      ("dic_result", dic.DicResult), ("dic_stats", dic.DicStats),
+                      ("dic_server_params", dic.DicServerParams), ("dic_server_stats", dic.DicServerStats)):
         assert lay[name] == C.sizeof(cls), name
         for field, _ in cls._fields_:
             key = "%s.%s" % (name, field)
@@ -86,6 +93,15 @@ def test_calls_without_a_device_fail_cleanly():
     assert L.dic_get_stats(None, None) == dic.DIC_E_INVAL
     assert L.dic_correlate(None, None, None, 0, None) == dic.DIC_E_INVAL
     assert dic.load_library().dic_last_error(None) == b"null context"
+    assert L.dic_server_create(None, 0, None, None) == dic.DIC_E_INVAL
+    prm = dic.DicServerParams(0, 1e9)
+    srv = C.c_void_p()
+    assert L.dic_server_create(C.byref(srv), 0, None, C.byref(prm)) == dic.DIC_E_INVAL
+    assert L.dic_server_step(None, 1) == dic.DIC_E_INVAL
+    assert L.dic_server_poll(None, 1, None, None, None) == dic.DIC_E_INVAL
+    assert L.dic_server_get_stats(None, None) == dic.DIC_E_INVAL
+    assert L.dic_server_destroy(None) == dic.DIC_E_INVAL
+    assert L.dic_server_last_error(None) == b"null server"
 
 
 def test_missing_library_raises(tmp_path, monkeypatch):
