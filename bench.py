@@ -176,6 +176,208 @@ def gigapixel(args, repeats=6, samples=24):
     eng.close()
 
 
+def serve(args):
+    """The serving mix: 8 resident 4096^2 u8 references; requests arrive as a
+    Poisson process (rate per second, fixed duration) and each correlates a
+    deformed centred S x S window (S from 256 to 4096) with its own subset
+    size (15..51), step (1, 2, 5) and random affine field.  Frames are rendered
+    and resident on the device before the clock starts.  Reference precomputes
+    are made resident on demand and the least recently used idle ones are
+    released when the HBM budget needs room; that registration time is inside
+    the measured latency.  Latency runs from the arrival on the virtual clock to
+    u, v, ZNCC and status on the host."""
+    import collections
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    from paper_2601_12941_amd import dic, synth
+
+    t00 = time.perf_counter()
+
+    def note(msg):
+        print("# %6.1f s  %s" % (time.perf_counter() - t00, msg), file=sys.stderr, flush=True)
+    trace = synth.serve_trace(args.duration, args.rate)
+    nref = 8
+    blobs = [synth.serve_reference_blobs(r) for r in range(nref)]
+    with ThreadPoolExecutor(4) as ex:
+        refs = list(ex.map(lambda r: synth.serve_reference(r, blobs[r]), range(nref)))
+    d_refs = [torch.from_numpy(r).cuda() for r in refs]
+    note("%d references rendered" % nref)
+    # a sample checked against the oracle afterwards: small windows only
+    rng = np.random.default_rng(7)
+    small = [q.index for q in trace if q.S <= 512 and q.N <= 31]
+    sample = set(rng.choice(small, min(args.parity_samples, len(small)), replace=False).tolist()) if small else set()
+    frames, host_frames = [None] * len(trace), {}
+    with ThreadPoolExecutor(4) as ex:
+        for q, f in zip(trace, ex.map(lambda q: synth.serve_frame(q, blobs[q.ref]), trace)):
+            frames[q.index] = torch.from_numpy(f).cuda()
+            if q.index in sample:
+                host_frames[q.index] = f
+            if q.index % 200 == 0:
+                note("frame %d of %d rendered" % (q.index, len(trace)))
+    rois = {S: torch.from_numpy(synth.serve_roi(S)).cuda() for S in synth.SERVE_SIZES}
+    torch.cuda.synchronize()
+    note("%d frames resident" % len(trace))
+
+    def window(r, S):
+        o = synth.serve_window(S)
+        return d_refs[r][o:o + S, o:o + S]
+
+    def params(N, st):
+        return dict(subset_size=N, step=st, shape=6, tol=1e-4, max_iter=50, zncc_min=0.7, seed_radius=8)
+
+    srv = dic.Server(0, max_active=args.max_active, hbm_budget_bytes=args.budget_gb * 1e9)
+    # warm-up: every kernel shape once on a 256^2 request, outside the clock
+    wq = min((q for q in trace if q.S == 256), key=lambda q: q.index, default=None)
+    for N in synth.SERVE_SUBSETS if wq is not None else ():
+        rid = srv.add_reference(window(wq.ref, 256), rois[256], **params(N, 5))
+        t, _ = srv.submit(rid, frames[wq.index], [(128.0, 128.0, 0.0, 0.0)])
+        while not srv.poll(t)[0]:
+            srv.step(8)
+        srv.remove_reference(rid)
+    torch.cuda.synchronize()
+    note("warm-up done")
+
+    resident = collections.OrderedDict()      # (ref, S, N, step) -> reference id, least recently used first
+    inuse = collections.Counter()
+    reg = dict(count=0, ms=0.0, evictions=0)
+
+    def ensure(q):
+        key = (q.ref, q.S, q.N, q.step)
+        if key in resident:
+            resident.move_to_end(key)
+            return resident[key]
+        while True:
+            t1 = time.perf_counter()
+            try:
+                rid = srv.add_reference(window(q.ref, q.S), rois[q.S], **params(q.N, q.step))
+            except dic.DicError as e:
+                if e.code != dic.DIC_E_NOMEM:
+                    raise
+                idle = [k for k, v in resident.items() if inuse[v] == 0]
+                if not idle:
+                    return None
+                srv.remove_reference(resident.pop(idle[0]))
+                reg["evictions"] += 1
+                continue
+            reg["count"] += 1
+            reg["ms"] += (time.perf_counter() - t1) * 1e3
+            resident[key] = rid
+            return rid
+
+    cs = torch.cuda.Stream()
+    pending = collections.deque()
+    inflight, copies = {}, []
+    done_at, conv = {}, {}
+    kept = {}
+    qlog = []
+    nxt = 0
+    next_log = 0.0
+    t0 = time.perf_counter()
+    while len(done_at) < len(trace):
+        now = time.perf_counter() - t0
+        while nxt < len(trace) and trace[nxt].arrival <= now:
+            pending.append(nxt)
+            nxt += 1
+        while pending:
+            q = trace[pending[0]]
+            rid = ensure(q)
+            if rid is None:
+                break
+            c = q.S / 2.0
+            t, out = srv.submit(rid, frames[q.index], [(c, c, 0.0, 0.0)])
+            inflight[t] = (q.index, out, rid)
+            inuse[rid] += 1
+            pending.popleft()
+        if inflight:
+            srv.step(args.chunk)
+            for t in list(inflight):
+                done, status, st = srv.poll(t)
+                if not done:
+                    continue
+                i, out, rid = inflight.pop(t)
+                inuse[rid] -= 1
+                if status != dic.DIC_OK:
+                    raise RuntimeError("request %d failed with status %d" % (i, status))
+                conv[i] = st["converged"]
+                cs.wait_stream(torch.cuda.current_stream())
+                with torch.cuda.stream(cs):
+                    host = {k: torch.empty(out[k][:2].shape if k == "p" else out[k].shape, dtype=out[k].dtype,
+                                           pin_memory=True) for k in ("p", "zncc", "status")}
+                    host["p"].copy_(out["p"][:2], non_blocking=True)
+                    host["zncc"].copy_(out["zncc"], non_blocking=True)
+                    host["status"].copy_(out["status"], non_blocking=True)
+                    ev = torch.cuda.Event()
+                    ev.record(cs)
+                copies.append((i, ev, host, out))
+        elif not pending and nxt < len(trace):
+            time.sleep(max(0.0, min(0.002, trace[nxt].arrival - (time.perf_counter() - t0))))
+        still = []
+        for i, ev, host, out in copies:
+            if ev.query():
+                done_at[i] = time.perf_counter() - t0
+                if i in sample:
+                    kept[i] = {k: v.numpy().copy() for k, v in host.items()}
+            else:
+                still.append((i, ev, host, out))
+        copies = still
+        now = time.perf_counter() - t0
+        if now >= next_log:
+            s = srv.stats()
+            qlog.append([round(now, 2), len(pending) + s["waiting"], s["active"], len(resident),
+                         round(s["used_bytes"] / 1e9, 1)])
+            next_log += 1.0
+    t_end = time.perf_counter() - t0
+    note("serving done")
+    lat = np.array([done_at[q.index] - q.arrival for q in trace]) * 1e3
+    sizes = {}
+    for q in trace:
+        sizes.setdefault(q.S, []).append(done_at[q.index] - q.arrival)
+    subsets = sum(conv.values())
+    offered = sum(np.prod(synth.grid_shape(q.S, q.S, q.N, q.step)) for q in trace) / args.duration
+    last_arrival = trace[-1].arrival
+    # sampled parity against the oracle, and error against the ground truth
+    errs, dz, agree, terr = [], [], [], []
+    for i in sorted(kept):
+        q = trace[i]
+        o = synth.serve_window(q.S)
+        refw = refs[q.ref][o:o + q.S, o:o + q.S]
+        r = oracle.correlate(np.ascontiguousarray(refw), host_frames[i], synth.serve_roi(q.S),
+                             seeds=[(q.S / 2.0, q.S / 2.0, 0.0, 0.0)], threads=16, **params(q.N, q.step))
+        g = kept[i]
+        both = (g["status"] == 0) & (r["status"] == 0)
+        act = r["status"] != oracle.ST["NOT_IN_ROI"]
+        agree.append(float((g["status"] == r["status"])[act].mean()))
+        if both.any():
+            errs.append(float(max(np.abs(g["p"][0] - r["p"][0])[both].max(), np.abs(g["p"][1] - r["p"][1])[both].max())))
+            dz.append(float(np.abs(g["zncc"] - r["zncc"])[both].max()))
+        u, v, _ = synth.truth_at_nodes(q.field(), q.S, q.S, q.N, q.step)
+        cg = g["status"] == 0
+        if cg.any():
+            terr.append(float(np.sqrt(((g["p"][0] - u) ** 2 + (g["p"][1] - v) ** 2)[cg].mean())))
+    note("sampled parity done")
+    rec = {"workload": "serving mix: 8 resident 4096^2 u8 references, Poisson %.0f req/s for %.0f s, windows "
+                       "256..4096, subsets 15..51, steps 1/2/5, affine" % (args.rate, args.duration),
+           "requests": len(trace), "max_active": args.max_active, "budget_gb": args.budget_gb,
+           "steps_per_call": args.chunk,
+           "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+           "latency_ms_p50_by_window": {str(S): float(np.percentile(np.array(v) * 1e3, 50)) for S, v in
+                                        sorted(sizes.items())},
+           "latency_ms_p99_by_window": {str(S): float(np.percentile(np.array(v) * 1e3, 99)) for S, v in
+                                        sorted(sizes.items())},
+           "offered_subsets_per_s": float(offered),
+           "served_converged_subsets_per_s": float(subsets / t_end), "converged_subsets": int(subsets),
+           "makespan_s": t_end, "drain_after_last_arrival_s": t_end - last_arrival,
+           "keeps_up": bool(t_end - last_arrival < 2.0),
+           "queue_per_second": {"columns": ["t_s", "queued", "active", "resident_refs", "used_gb"], "rows": qlog},
+           "registrations": reg["count"], "registration_ms_total": reg["ms"], "evictions": reg["evictions"],
+           "sampled_parity": {"requests": len(kept), "max_duv_px": max(errs) if errs else None,
+                              "max_dzncc": max(dz) if dz else None, "min_status_agree": min(agree) if agree else None},
+           "error_vs_truth_rms_px_max_over_sample": max(terr) if terr else None}
+    print(json.dumps(rec))
+    srv.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,20 +390,30 @@ def main():
     ap.add_argument("--tps", type=int, default=64, help="threads per subset, batched form")
     ap.add_argument("--plain-tps", type=int, default=128, help="threads per subset, plain form")
     ap.add_argument("--cpu-crop", type=int, default=2048, help="oracle sample window (0 = skip)")
-    ap.add_argument("--workload", default="2048", choices=["2048", "gigapixel"],
-                    help="2048: the 2048^2 batched/plain benchmark; gigapixel: the 32768^2 pair, repeated")
+    ap.add_argument("--workload", default="2048", choices=["2048", "gigapixel", "serve"],
+                    help="2048: the 2048^2 batched/plain benchmark; gigapixel: the 32768^2 pair, repeated; "
+                         "serve: the serving mix")
+    ap.add_argument("--duration", type=float, default=60.0, help="serve: seconds of Poisson arrivals")
+    ap.add_argument("--rate", type=float, default=20.0, help="serve: requests per second")
+    ap.add_argument("--max-active", type=int, default=48, help="serve: requests on the device at once")
+    ap.add_argument("--budget-gb", type=float, default=170.0, help="serve: library HBM budget")
+    ap.add_argument("--chunk", type=int, default=8, help="serve: launch steps per server call")
+    ap.add_argument("--parity-samples", type=int, default=8, help="serve: requests checked against the oracle")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
         return
-    if args.workload == "gigapixel":
-        gigapixel(args)
-        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "serve":
+        serve(args)
+        return
+    if args.workload == "gigapixel":
+        gigapixel(args)
+        return
 
     import torch
     from paper_2601_12941_amd import dic, synth

@@ -208,9 +208,16 @@ typedef struct {
 dic_status dic_server_create(dic_server **out, int device, void *hip_stream, const dic_server_params *prm);
 
 /* Make a reference resident (same arguments as dic_set_reference); *ref_id
- * names it in later submissions.  Fails with DIC_E_NOMEM beyond the budget. */
+ * names it in later submissions.  Fails with DIC_E_NOMEM, before allocating,
+ * when its precompute does not fit the budget next to the resident references
+ * and active requests (idle pooled scratch is released first). */
 dic_status dic_server_add_reference(dic_server *s, const dic_image *ref, const uint8_t *roi_mask_dev,
                                     const dic_params *prm, int32_t *ref_id);
+
+/* Release a resident reference and its pooled request scratch.  Fails with
+ * DIC_E_STATE while a waiting or active request uses it; its id is not
+ * reused.  Tickets of finished requests stay pollable. */
+dic_status dic_server_remove_reference(dic_server *s, int32_t ref_id);
 
 /* Queue a request: deformed image (DEVICE, same size as the reference),
  * host seeds, caller-allocated DEVICE results.  *ticket identifies it.  The

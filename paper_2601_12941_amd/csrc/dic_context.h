@@ -183,22 +183,59 @@ inline dic_status ensure_frames(dic_ctx *c, int n)
 }
 
 // Nearest active node to (x, y), ties to smaller y then smaller x; -1 if none.
+// Searches square rings of grid nodes around the node nearest to (x, y) and
+// stops once a ring cannot hold a node closer than the best found.
 inline int64_t snap_seed(const dic_ctx *c, double x, double y)
 {
     const int h = (c->prm.subset_size - 1) / 2, s = c->prm.step;
+    const int nx = c->nx, ny = c->ny;
+    if (nx < 1 || ny < 1) return -1;
+    auto clampi = [](double v, int hi) { return v < 0.0 ? 0 : (v > hi ? hi : static_cast<int>(std::lround(v))); };
+    const int i0 = clampi((x - h) / s, nx - 1), j0 = clampi((y - h) / s, ny - 1);
     int64_t best = -1;
     double bd = 0.0;
-    for (int j = 0; j < c->ny; ++j)
-        for (int i = 0; i < c->nx; ++i) {
-            const int64_t node = static_cast<int64_t>(j) * c->nx + i;
-            if (c->flag_host[node] < 0) continue;
-            const double dx = h + i * s - x, dy = h + j * s - y;
-            const double d = dx * dx + dy * dy;
-            if (best < 0 || d < bd) {
-                best = node;
-                bd = d;
+    int bj = 0, bi = 0;
+    auto consider = [&](int i, int j) {
+        const int64_t node = static_cast<int64_t>(j) * nx + i;
+        if (c->flag_host[node] < 0) return;
+        const double dx = h + static_cast<double>(i) * s - x, dy = h + static_cast<double>(j) * s - y;
+        const double d = dx * dx + dy * dy;
+        if (best < 0 || d < bd || (d == bd && (j < bj || (j == bj && i < bi)))) {
+            best = node;
+            bd = d;
+            bj = j;
+            bi = i;
+        }
+    };
+    // every node of ring r has |i - i0| = r or |j - j0| = r, so it lies at least
+    // min(gap_x(r), gap_y(r)) from (x, y)
+    auto gap = [&](int r, int k0, int n, double v) {
+        double g = -1.0;
+        for (int k : {k0 - r, k0 + r}) {
+            if (k < 0 || k >= n) continue;
+            const double dd = std::fabs(h + static_cast<double>(k) * s - v);
+            g = g < 0.0 ? dd : std::min(g, dd);
+        }
+        return g;
+    };
+    const int rmax = std::max(nx, ny);
+    for (int r = 0; r <= rmax; ++r) {
+        if (best >= 0) {
+            const double gx = gap(r, i0, nx, x), gy = gap(r, j0, ny, y);
+            double lb = gx < 0.0 ? gy : (gy < 0.0 ? gx : std::min(gx, gy));
+            if (lb >= 0.0 && lb * lb > bd) break;
+        }
+        const int ja = std::max(0, j0 - r), jb = std::min(ny - 1, j0 + r);
+        const int ia = std::max(0, i0 - r), ib = std::min(nx - 1, i0 + r);
+        for (int j = ja; j <= jb; ++j) {
+            if (j == j0 - r || j == j0 + r) {
+                for (int i = ia; i <= ib; ++i) consider(i, j);
+            } else {
+                if (i0 - r >= 0) consider(i0 - r, j);
+                if (r > 0 && i0 + r < nx) consider(i0 + r, j);
             }
         }
+    }
     return best;
 }
 

@@ -381,151 +381,225 @@ __device__ __forceinline__ void steepest(double (&J)[NP], double gx, double gy, 
 constexpr double kFlatRel = 1e-6;
 constexpr double kSingularRel = 1e-10;
 
+// Slot of sum-group B entry i in the per-node cache: entries 0..NP-1 (sum J) go
+// to slots 3..3+NP-1, entries NP.. (sum J J^T, upper triangle by rows) to the
+// Hessian slots 3+2NP.. .
+template <int NP> __device__ __forceinline__ int slot_b(int i) { return i < NP ? 3 + i : 3 + NP + i; }
+
+// Per-node sums over the reference subset, written raw to the cache (slot
+// layout as read by the wave kernel; k_ref_factor then turns them into the
+// cached quantities).  Group A, the sums the iteration recomputes for the
+// deformed subset (sum fbar, sum fbar^2, sum J fbar), is reduced exactly as the
+// iteration reduces its own, so that an identical deformed subset reproduces
+// them bitwise.  Group B (sum J and sum J J^T, FP64 per lane) is reduced by a
+// pair exchange and an LDS transpose, in a fixed order.
 template <int NP, int T, int P>
 __global__ __launch_bounds__(T) void k_ref_nodes(RefView R, double *cache, int8_t *flag)
 {
     constexpr int NH = NP * (NP + 1) / 2;
-    constexpr int NV = 3 + NP + NP + NH;
-    __shared__ double red[2 * (T / 64) * NV];
+    constexpr int NB = NP + NH;
+    constexpr int NW = T / 64;
+    constexpr int CH = NB < 32 ? NB : 32;      // group-B entries per LDS pass
+    constexpr int LS = 33;                      // LDS row stride (doubles) of one entry
+    __shared__ double red[2 * NW * (3 + NP)];
+    __shared__ double tr[NW * CH * LS];
+    __shared__ double part[NW * CH];
     int parity = 0;
     const int N = R.N, h = (N - 1) / 2, n = N * N;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const Columns L(t, T, N);
     const float dxf = static_cast<float>(L.c - h);
     const float dy0 = static_cast<float>(L.r0 - h), dyR = static_cast<float>(L.R);
-    for (int64_t node = blockIdx.x; node < R.nodes; node += gridDim.x) {
+    const int64_t nn = R.nodes;
+    const int64_t rstep = static_cast<int64_t>(L.R) * R.ppitch;
+    for (int64_t node = blockIdx.x; node < nn; node += gridDim.x) {
         if (flag[node] < 0) continue;
         const int xc = h + static_cast<int>(node % R.nx) * R.step;
         const int yc = h + static_cast<int>(node / R.nx) * R.step;
-        float fv[P], gxv[P], gyv[P];
+        const int64_t o0 = static_cast<int64_t>(yc - h + L.r0) * R.ppitch + xc - h + L.c;
         double sf[1] = {0.0};
 #pragma unroll
-        for (int j = 0; j < P; ++j) {
-            fv[j] = gxv[j] = gyv[j] = 0.0f;
-            if (j < L.jmax) {
-                const int64_t o = static_cast<int64_t>(yc - h + L.r0 + L.R * j) * R.ppitch + xc - h + L.c;
-                fv[j] = R.pf[o];
-                gxv[j] = R.pfx[o];
-                gyv[j] = R.pfy[o];
-                sf[0] += static_cast<double>(fv[j]);
-            }
-        }
+        for (int j = 0; j < P; ++j)
+            if (j < L.jmax) sf[0] += static_cast<double>(R.pf[o0 + j * rstep]);
         block_allreduce<T, 1>(sf, red, parity);
         const double fm = sf[0] / n;
         const float fm32 = static_cast<float>(fm);
         float s[3 + NP];
 #pragma unroll
         for (int i = 0; i < 3 + NP; ++i) s[i] = 0.0f;
-        double v[NV];
+        double vb[NB];
 #pragma unroll
-        for (int i = 0; i < NV; ++i) v[i] = 0.0;
+        for (int i = 0; i < NB; ++i) vb[i] = 0.0;
 #pragma unroll
         for (int j = 0; j < P; ++j) {
             if (j < L.jmax) {
-                const float fb = fv[j] - fm32;
+                const int64_t o = o0 + j * rstep;
+                const float fb = R.pf[o] - fm32;
+                const float gx = R.pfx[o], gy = R.pfy[o];
                 const float dyf = fmaf(static_cast<float>(j), dyR, dy0);
-                accumulate<NP>(s, fb, fb, gxv[j], gyv[j], dxf, dyf);
+                accumulate<NP>(s, fb, fb, gx, gy, dxf, dyf);
                 double J[NP];
-                steepest<NP>(J, gxv[j], gyv[j], dxf, dyf);
-                int q = 3 + NP + NP;
+                steepest<NP>(J, gx, gy, dxf, dyf);
+                int q = NP;
 #pragma unroll
                 for (int a = 0; a < NP; ++a) {
-                    v[3 + NP + a] += J[a];
+                    vb[a] += J[a];
 #pragma unroll
                     for (int b = a; b < NP; ++b) {
-                        v[q] = fma(J[a], J[b], v[q]);
+                        vb[q] = fma(J[a], J[b], vb[q]);
                         ++q;
                     }
                 }
             }
         }
+        double va[3 + NP];
 #pragma unroll
-        for (int i = 0; i < 3 + NP; ++i) v[i] = static_cast<double>(s[i]);
-        block_allreduce<T, NV>(v, red, parity);
+        for (int i = 0; i < 3 + NP; ++i) va[i] = static_cast<double>(s[i]);
+        block_allreduce<T, 3 + NP>(va, red, parity);
         if (t == 0) {
-            // same expressions as the iteration's dg2 and J^T gbar, so that an
-            // identical deformed subset gives a bitwise-zero increment
-            const double S0 = v[0], S1 = v[1];
-            const double gm = S0 * (1.0 / n);
-            const double df2 = S1 - S0 * gm;
-            double SJ[NP], SJf[NP];
+            cache[node] = fm;
+            cache[1 * nn + node] = va[1];
+            cache[2 * nn + node] = va[0];
 #pragma unroll
-            for (int a = 0; a < NP; ++a) {
-                SJ[a] = v[3 + NP + a];
-                SJf[a] = v[3 + a] - gm * SJ[a];
+            for (int a = 0; a < NP; ++a) cache[(3 + NP + a) * nn + node] = va[3 + a];
+        }
+        // group B: lanes 2k and 2k+1 pair up, then entry i of the 32 pair sums of
+        // every wavefront sits in an LDS row that one lane adds up
+#pragma unroll
+        for (int i = 0; i < NB; ++i) vb[i] += dpp_read<0xB1>(vb[i]);
+#pragma unroll
+        for (int c0 = 0; c0 < NB; c0 += CH) {
+            if ((lane & 1) == 0) {
+#pragma unroll
+                for (int i = 0; i < CH; ++i)
+                    if (c0 + i < NB) tr[(w * CH + i) * LS + (lane >> 1)] = vb[c0 + i];
             }
-            int8_t st = 0;
-            const double lev = fmax(1.0, fabs(fm));
-            if (isnan(df2)) st = kNan;
-            else if (df2 <= n * (kFlatRel * lev) * (kFlatRel * lev)) st = kFlatRef;
-            // centred Hessian H = sum J J^T - SJ SJ^T / n, Cholesky L L^T
-            double L[NP][NP];
-            double Hd[NP];
-            {
-                int q = 3 + NP + NP;
+            __syncthreads();
+            double tot = 0.0;
+            if (lane < CH && c0 + lane < NB) {
+                const double *row = tr + (w * CH + lane) * LS;
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
-                for (int a = 0; a < NP; ++a)
-#pragma unroll
-                    for (int b = a; b < NP; ++b) {
-                        const double hv = v[q++] - SJ[a] * SJ[b] / n;
-                        L[a][b] = hv;
-                        L[b][a] = hv;
-                    }
+                for (int k = 0; k < 32; k += 4) {
+                    a0 += row[k];
+                    a1 += row[k + 1];
+                    a2 += row[k + 2];
+                    a3 += row[k + 3];
+                }
+                tot = (a0 + a1) + (a2 + a3);
             }
-            double hmax = 0.0, scl[NP];
+            if constexpr (NW > 1) {
+                if (lane < CH) part[w * CH + lane] = tot;
+                __syncthreads();
+                if (w == 0 && lane < CH) {
+                    tot = part[lane];
 #pragma unroll
-            for (int a = 0; a < NP; ++a) {
-                scl[a] = a < 2 ? 1.0 : (a < 6 ? static_cast<double>(h) * h : static_cast<double>(h) * h * h * h);
-                Hd[a] = L[a][a];
-                hmax = fmax(hmax, Hd[a] / scl[a]);
-            }
-            // in-place Cholesky on the lower triangle
-            for (int a = 0; a < NP && st == 0; ++a) {
-                double d = L[a][a];
-                for (int k = 0; k < a; ++k) d -= L[a][k] * L[a][k];
-                if (isnan(d)) { st = kNan; break; }
-                if (!(d > kSingularRel * scl[a] * hmax)) { st = kSingular; break; }
-                const double la = sqrt(d);
-                L[a][a] = la;
-                for (int i = a + 1; i < NP; ++i) {
-                    double x = L[i][a];
-                    for (int k = 0; k < a; ++k) x -= L[i][k] * L[a][k];
-                    L[i][a] = x / la;
+                    for (int ww = 1; ww < NW; ++ww) tot += part[ww * CH + lane];
                 }
             }
-            double *c = cache;
-            const int64_t nn = R.nodes;
-            c[0 * nn + node] = fm;
-            c[1 * nn + node] = df2;
-            c[2 * nn + node] = S0;
-#pragma unroll
-            for (int a = 0; a < NP; ++a) {
-                c[(3 + a) * nn + node] = SJ[a];
-                c[(3 + NP + a) * nn + node] = SJf[a];
-            }
-            if (st == 0) {
-                // H^{-1} = L^{-T} L^{-1}; Li = L^{-1} (lower), column by column
-                double Li[NP][NP];
-                for (int j = 0; j < NP; ++j) {
-                    for (int i = 0; i < NP; ++i) Li[i][j] = 0.0;
-                    Li[j][j] = 1.0 / L[j][j];
-                    for (int i = j + 1; i < NP; ++i) {
-                        double x = 0.0;
-                        for (int k = j; k < i; ++k) x -= L[i][k] * Li[k][j];
-                        Li[i][j] = x / L[i][i];
-                    }
-                }
-                int q = 3 + 2 * NP;
-                for (int a = 0; a < NP; ++a)
-                    for (int b = a; b < NP; ++b) {
-                        double x = 0.0;
-                        for (int k = b; k < NP; ++k) x += Li[k][a] * Li[k][b];
-                        c[static_cast<int64_t>(q++) * nn + node] = x;
-                    }
-            }
-            flag[node] = st;
+            if (w == 0 && lane < CH && c0 + lane < NB)
+                cache[static_cast<int64_t>(slot_b<NP>(c0 + lane)) * nn + node] = tot;
+            __syncthreads();
         }
     }
+}
+
+// Packed lower-triangle index (row i, column j <= i).
+__host__ __device__ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// One thread per node: from the raw sums, the reference deviation, the
+// centred sums sum J fbar, the flat and singular checks, and the inverse of
+// the centred Gauss-Newton Hessian (Cholesky, inverse of the factor, product),
+// all in FP64 and fully unrolled.
+template <int NP>
+__global__ __launch_bounds__(256) void k_ref_factor(RefView R, double *cache, int8_t *flag)
+{
+    constexpr int NH = NP * (NP + 1) / 2;
+    const int64_t node = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t nn = R.nodes;
+    if (node >= nn || flag[node] < 0) return;
+    const int N = R.N, h = (N - 1) / 2, n = N * N;
+    double *c = cache + node;
+    const double fm = c[0], S1 = c[1 * nn], S0 = c[2 * nn];
+    // same expressions as the iteration's dg2 and J^T gbar, so that an
+    // identical deformed subset gives a bitwise-zero increment
+    const double gm = S0 * (1.0 / n);
+    const double df2 = S1 - S0 * gm;
+    double SJ[NP];
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+        SJ[a] = c[(3 + a) * nn];
+        c[(3 + NP + a) * nn] = c[(3 + NP + a) * nn] - gm * SJ[a];
+    }
+    c[1 * nn] = df2;
+    int8_t st = 0;
+    const double lev = fmax(1.0, fabs(fm));
+    if (isnan(df2)) st = kNan;
+    else if (df2 <= n * (kFlatRel * lev) * (kFlatRel * lev)) st = kFlatRef;
+    // centred Hessian H = sum J J^T - SJ SJ^T / n, lower triangle
+    double Lm[NH];
+    {
+        int q = 0;
+#pragma unroll
+        for (int a = 0; a < NP; ++a)
+#pragma unroll
+            for (int b = a; b < NP; ++b) {
+                Lm[tri(b, a)] = c[static_cast<int64_t>(3 + 2 * NP + q) * nn] - SJ[a] * SJ[b] / n;
+                ++q;
+            }
+    }
+    double hmax = 0.0;
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+        const double scl = a < 2 ? 1.0 : (a < 6 ? static_cast<double>(h) * h : static_cast<double>(h) * h * h * h);
+        hmax = fmax(hmax, Lm[tri(a, a)] / scl);
+    }
+    // in-place Cholesky; the first failing pivot sets the status and the rest
+    // runs on a unit pivot (its output is discarded)
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+        const double scl = a < 2 ? 1.0 : (a < 6 ? static_cast<double>(h) * h : static_cast<double>(h) * h * h * h);
+        double d = Lm[tri(a, a)];
+#pragma unroll
+        for (int k = 0; k < a; ++k) d -= Lm[tri(a, k)] * Lm[tri(a, k)];
+        if (st == 0) {
+            if (isnan(d)) st = kNan;
+            else if (!(d > kSingularRel * scl * hmax)) st = kSingular;
+        }
+        const double la = st == 0 ? sqrt(d) : 1.0;
+        Lm[tri(a, a)] = la;
+#pragma unroll
+        for (int i = a + 1; i < NP; ++i) {
+            double x = Lm[tri(i, a)];
+#pragma unroll
+            for (int k = 0; k < a; ++k) x -= Lm[tri(i, k)] * Lm[tri(a, k)];
+            Lm[tri(i, a)] = x / la;
+        }
+    }
+    // L^{-1} in place, column by column; then H^{-1} = L^{-T} L^{-1} (upper, by rows)
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const double dj = 1.0 / Lm[tri(j, j)];
+#pragma unroll
+        for (int i = j + 1; i < NP; ++i) {
+            double x = 0.0;
+#pragma unroll
+            for (int k = j; k < i; ++k) x -= Lm[tri(i, k)] * (k == j ? dj : Lm[tri(k, j)]);
+            Lm[tri(i, j)] = x / Lm[tri(i, i)];
+        }
+        Lm[tri(j, j)] = dj;
+    }
+    int q = 3 + 2 * NP;
+#pragma unroll
+    for (int a = 0; a < NP; ++a)
+#pragma unroll
+        for (int b = a; b < NP; ++b) {
+            double x = 0.0;
+#pragma unroll
+            for (int k = b; k < NP; ++k) x += Lm[tri(k, a)] * Lm[tri(k, b)];
+            c[static_cast<int64_t>(q++) * nn] = st == 0 ? x : 0.0;
+        }
+    flag[node] = st;
 }
 
 template <int NP, int T, int P>
@@ -533,6 +607,7 @@ static void ref_nodes_inst(const RefView &R, double *cache, int8_t *flag, hipStr
 {
     const int64_t blocks = R.nodes < 8192 ? R.nodes : 8192;
     k_ref_nodes<NP, T, P><<<static_cast<unsigned>(blocks < 1 ? 1 : blocks), T, 0, s>>>(R, cache, flag);
+    k_ref_factor<NP><<<static_cast<unsigned>((R.nodes + 255) / 256), 256, 0, s>>>(R, cache, flag);
 }
 
 // ---------------------------------------------------------------------------

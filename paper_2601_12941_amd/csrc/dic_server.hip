@@ -66,11 +66,15 @@ size_t request_bytes(const dic_ctx *c)
            sizeof(FrameState);
 }
 
-size_t reference_bytes(const dic_ctx *c)
+// Device bytes dic_set_reference allocates for an image of W x H pixels.
+size_t reference_bytes(int W, int H, int pixel, const dic_params &p)
 {
-    return c->coef_elems() * sizeof(float) + sizeof(float) * c->tpitch * c->H + 3 * sizeof(float) * c->ppitch * c->H +
-           sizeof(double) * cache_slots(c->np) * c->nodes + c->nodes + c->W * pixel_size(c->ref_pixel) * c->H +
-           sizeof(int32_t) * (c->nodes + 130) + sizeof(RefView);
+    const int64_t nx = (W - p.subset_size) / p.step + 1, ny = (H - p.subset_size) / p.step + 1;
+    const size_t nodes = static_cast<size_t>(nx) * ny;
+    const size_t cpitch = round_up(W + 2 * kPad, 64), ppitch = round_up(W, 64);
+    return cpitch * (H + 2 * kPad) * sizeof(float) + ppitch * H * sizeof(float) * 4 +
+           sizeof(double) * cache_slots(p.shape) * nodes + nodes + static_cast<size_t>(W) * pixel_size(pixel) * H +
+           sizeof(int32_t) * (nodes + 130) + sizeof(RefView);
 }
 
 } // namespace
@@ -80,7 +84,8 @@ struct dic_server {
     hipStream_t stream = nullptr;
     dic_server_params prm{};
     std::string err;
-    std::vector<dic_ctx *> refs;
+    std::vector<dic_ctx *> refs;        // nullptr once removed
+    std::vector<double> ref_size;       // bytes counted for each reference
     std::deque<Request *> waiting;
     std::vector<Request *> active;
     std::unordered_map<int64_t, Request *> all;
@@ -299,6 +304,16 @@ dic_status dic_server_add_reference(dic_server *s, const dic_image *ref, const u
 {
     if (!s || !ref_id) return DIC_E_INVAL;
     s->err.clear();
+    if (!ref || !prm) SFAIL(DIC_E_INVAL, "reference image or params is NULL");
+    if (ref->width >= prm->subset_size && ref->height >= prm->subset_size && prm->step >= 1 &&
+        (prm->shape == DIC_SHAPE_AFFINE || prm->shape == DIC_SHAPE_QUADRATIC)) {
+        // budget check before anything is allocated; idle pooled scratch goes first
+        const double bytes = static_cast<double>(reference_bytes(ref->width, ref->height, ref->pixel, *prm));
+        if (s->ref_bytes + s->active_bytes + s->pool_bytes + bytes > s->prm.hbm_budget_bytes) trim_pool(s, bytes);
+        if (s->ref_bytes + s->active_bytes + s->pool_bytes + bytes > s->prm.hbm_budget_bytes)
+            SFAIL(DIC_E_NOMEM, "reference of %.0f MB exceeds the HBM budget (%.0f MB in use)", bytes / 1e6,
+                  (s->ref_bytes + s->active_bytes) / 1e6);
+    }
     SHIP(hipSetDevice(s->device));
     dic_ctx *c = nullptr;
     dic_status rc = dic_create(&c, s->device, s->stream);
@@ -309,17 +324,40 @@ dic_status dic_server_add_reference(dic_server *s, const dic_image *ref, const u
         dic_destroy(c);
         return rc;
     }
-    const double bytes = static_cast<double>(reference_bytes(c));
-    if (s->ref_bytes + s->active_bytes + bytes > s->prm.hbm_budget_bytes) {
-        trim_pool(s, bytes);
-        if (s->ref_bytes + s->active_bytes + bytes > s->prm.hbm_budget_bytes) {
-            dic_destroy(c);
-            SFAIL(DIC_E_NOMEM, "reference of %.0f MB exceeds the HBM budget", bytes / 1e6);
-        }
-    }
+    const double bytes = static_cast<double>(reference_bytes(c->W, c->H, c->ref_pixel, c->prm));
     s->ref_bytes += bytes;
     s->refs.push_back(c);
+    s->ref_size.push_back(bytes);
     *ref_id = static_cast<int32_t>(s->refs.size() - 1);
+    return DIC_OK;
+}
+
+dic_status dic_server_remove_reference(dic_server *s, int32_t ref_id)
+{
+    if (!s) return DIC_E_INVAL;
+    s->err.clear();
+    if (ref_id < 0 || ref_id >= static_cast<int32_t>(s->refs.size()) || !s->refs[ref_id])
+        SFAIL(DIC_E_INVAL, "unknown reference %d", ref_id);
+    dic_ctx *c = s->refs[ref_id];
+    for (const Request *r : s->waiting)
+        if (r->ref == c) SFAIL(DIC_E_STATE, "reference %d has waiting requests", ref_id);
+    for (const Request *r : s->active)
+        if (r->ref == c) SFAIL(DIC_E_STATE, "reference %d has active requests", ref_id);
+    SHIP(hipSetDevice(s->device));
+    auto it = s->pool.find(c);
+    if (it != s->pool.end()) {
+        for (ReqBuf *b : it->second) {
+            s->pool_bytes -= b->bytes;
+            free_buf(b);
+        }
+        s->pool.erase(it);
+    }
+    // finished requests keep their ticket but no longer point at the context
+    for (auto &kv : s->all)
+        if (kv.second->ref == c) kv.second->ref = nullptr;
+    dic_destroy(c);
+    s->refs[ref_id] = nullptr;
+    s->ref_bytes -= s->ref_size[ref_id];
     return DIC_OK;
 }
 
@@ -328,7 +366,8 @@ dic_status dic_server_submit(dic_server *s, int32_t ref_id, const dic_image *def
 {
     if (!s || !ticket) return DIC_E_INVAL;
     s->err.clear();
-    if (ref_id < 0 || ref_id >= static_cast<int32_t>(s->refs.size())) SFAIL(DIC_E_INVAL, "unknown reference %d", ref_id);
+    if (ref_id < 0 || ref_id >= static_cast<int32_t>(s->refs.size()) || !s->refs[ref_id])
+        SFAIL(DIC_E_INVAL, "unknown reference %d", ref_id);
     dic_ctx *c = s->refs[ref_id];
     if (!def || !def->data) SFAIL(DIC_E_INVAL, "deformed image is NULL");
     if (def->width != c->W || def->height != c->H) SFAIL(DIC_E_INVAL, "deformed image size differs from the reference");
@@ -514,7 +553,8 @@ dic_status dic_server_destroy(dic_server *s)
     }
     for (auto &kv : s->pool)
         for (ReqBuf *b : kv.second) free_buf(b);
-    for (dic_ctx *c : s->refs) dic_destroy(c);
+    for (dic_ctx *c : s->refs)
+        if (c) dic_destroy(c);
     dfree(s->d_frames);
     dfree(s->d_next);
     if (s->h_next) (void)hipHostFree(s->h_next);

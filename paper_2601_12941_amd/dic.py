@@ -30,8 +30,9 @@ NODE = dict(CONVERGED=0, NOT_REACHED=1, NOT_IN_ROI=2, MAX_ITER=3, LOW_ZNCC=4, OU
 # exported names, in the order include/dic.h declares them
 EXPORTS = ["dic_create", "dic_set_reference", "dic_grid_shape", "dic_correlate", "dic_correlate_batch",
            "dic_get_stats", "dic_destroy", "dic_last_error",
-           "dic_server_create", "dic_server_add_reference", "dic_server_submit", "dic_server_step",
-           "dic_server_poll", "dic_server_get_stats", "dic_server_destroy", "dic_server_last_error"]
+           "dic_server_create", "dic_server_add_reference", "dic_server_remove_reference", "dic_server_submit",
+           "dic_server_step", "dic_server_poll", "dic_server_get_stats", "dic_server_destroy",
+           "dic_server_last_error"]
 
 
 class DicImage(C.Structure):
@@ -96,6 +97,7 @@ def load_library(path: str = LIB_PATH):
     L.dic_last_error.restype = C.c_char_p
     L.dic_server_create.argtypes = [P(C.c_void_p), C.c_int, C.c_void_p, P(DicServerParams)]
     L.dic_server_add_reference.argtypes = [C.c_void_p, P(DicImage), C.c_void_p, P(DicParams), P(C.c_int32)]
+    L.dic_server_remove_reference.argtypes = [C.c_void_p, C.c_int32]
     L.dic_server_submit.argtypes = [C.c_void_p, C.c_int32, P(DicImage), P(DicSeed), C.c_int32, P(DicResult),
                                     P(C.c_int64)]
     L.dic_server_step.argtypes = [C.c_void_p, C.c_int32]
@@ -193,6 +195,10 @@ def dic_server_add_reference(srv, image: DicImage, roi_ptr: int, params: DicPara
     _scheck(srv, load_library().dic_server_add_reference(srv, C.byref(image), C.c_void_p(roi_ptr or 0),
                                                          C.byref(params), C.byref(rid)))
     return rid.value
+
+
+def dic_server_remove_reference(srv, ref_id: int):
+    _scheck(srv, load_library().dic_server_remove_reference(srv, int(ref_id)))
 
 
 def dic_server_submit(srv, ref_id: int, image: DicImage, seeds: Sequence[DicSeed], result: DicResult) -> int:
@@ -391,6 +397,10 @@ class Server:
         nx, ny = _grid(prm.subset_size, prm.step, ref.shape[1], ref.shape[0])
         self._refs[rid] = (ref, roi, prm.shape, nx, ny)
         return rid
+
+    def remove_reference(self, ref_id: int):
+        dic_server_remove_reference(self.srv, ref_id)
+        self._refs.pop(ref_id, None)
 
     def submit(self, ref_id: int, deformed, seeds):
         import torch

@@ -359,3 +359,95 @@ def workload(name: str, size: Optional[int] = None, **over) -> Workload:
         raise ValueError(name)
     d.update(over)
     return Workload(**d)
+
+
+# --------------------------------------------------------------------------
+# serving mix: resident 4096^2 references, requests on centred windows
+# --------------------------------------------------------------------------
+SERVE_REF_SIZE = 4096
+SERVE_SIZES = (256, 512, 1024, 2048, 4096)
+SERVE_SUBSETS = (15, 21, 31, 51)
+SERVE_STEPS = (1, 2, 5)
+SERVE_DENSITY = 3000 / 512 ** 2          # blobs per px^2, as the 512^2 u8 workload
+
+
+@dataclasses.dataclass
+class ServeRequest:
+    index: int
+    arrival: float            # seconds from the start of the run
+    ref: int                  # 0..7
+    S: int                    # window side
+    N: int
+    step: int
+    t: tuple                  # (tx, ty) at the window centre
+    grad: tuple               # (du/dx, du/dy, dv/dx, dv/dy) about the window centre
+
+    def field(self) -> Field:
+        c = self.S / 2.0
+        return field_affine(self.t[0], self.t[1], *self.grad, xc=c, yc=c)
+
+
+def serve_trace(duration: float = 60.0, rate: float = 20.0, seed: int = 5000, nrefs: int = 8):
+    """Poisson arrivals at `rate` per second over `duration` seconds; each request
+    draws a reference, a window size, a subset size and a step uniformly, a
+    translation uniform in the disc of radius 5 px and gradient entries uniform
+    in [-0.01, 0.01]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out, t = [], 0.0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            break
+        ref = int(rng.integers(nrefs))
+        S = int(SERVE_SIZES[rng.integers(len(SERVE_SIZES))])
+        N = int(SERVE_SUBSETS[rng.integers(len(SERVE_SUBSETS))])
+        st = int(SERVE_STEPS[rng.integers(len(SERVE_STEPS))])
+        r = 5.0 * math.sqrt(rng.uniform())
+        a = rng.uniform(0.0, 2.0 * math.pi)
+        g = tuple(float(x) for x in rng.uniform(-0.01, 0.01, 4))
+        out.append(ServeRequest(len(out), t, ref, S, N, st, (r * math.cos(a), r * math.sin(a)), g))
+    return out
+
+
+def serve_reference_blobs(ref: int):
+    W = SERVE_REF_SIZE
+    return draw_blobs(W, W, int(round(SERVE_DENSITY * W * W)), (2.0, 4.0), (60.0, 200.0), 5001 + ref)
+
+
+def serve_reference(ref: int, blobs=None) -> np.ndarray:
+    """The 4096^2 u8 reference image `ref` (blob seed 5001+ref, noise seed 5011+ref)."""
+    W = SERVE_REF_SIZE
+    X, Y, S, A = blobs if blobs is not None else serve_reference_blobs(ref)
+    return _finish(_render_blobs_large(W, W, X, Y, S, A), 2.0, 5011 + ref, 8)
+
+
+def serve_window(S: int):
+    """Origin of the centred S x S window in the reference."""
+    return (SERVE_REF_SIZE - S) // 2
+
+
+def serve_margin(S: int) -> int:
+    """ROI margin of a window: 4 px of interpolation support plus the largest
+    displacement the request fields reach (5 px + 0.02 * S / 2)."""
+    return 10 + int(math.ceil(0.01 * S))
+
+
+def serve_roi(S: int) -> np.ndarray:
+    m = serve_margin(S)
+    roi = np.zeros((S, S), np.uint8)
+    roi[m:S - m, m:S - m] = 1
+    return roi
+
+
+def serve_frame(req: ServeRequest, blobs) -> np.ndarray:
+    """Deformed S x S window of request `req` (noise seed 5100 + index): the
+    reference blobs near the window, moved by the request's field evaluated at
+    their reference position, in window coordinates."""
+    X, Y, S_, A = blobs
+    o = serve_window(req.S)
+    pad = 64.0
+    sel = (X >= o - pad) & (X < o + req.S + pad) & (Y >= o - pad) & (Y < o + req.S + pad)
+    x, y = X[sel] - o, Y[sel] - o
+    u, v = req.field()(x, y)
+    img = _render_blobs_large(req.S, req.S, x + u, y + v, S_[sel], A[sel])
+    return _finish(img, 2.0, 5100 + req.index, 8)

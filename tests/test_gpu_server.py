@@ -203,3 +203,53 @@ def test_request_errors():
     done, status, _ = srv.poll(t)
     assert done and status == dic.DIC_E_NOSEED
     srv.close()
+
+
+def test_remove_reference_frees_budget():
+    import torch
+    w = synth.workload("c1", size=192)
+    pair = w.pair()
+    roi = torch.from_numpy(np.ascontiguousarray(pair.roi)).cuda()
+    ref = dic.to_device_image(pair.ref)
+    de = dic.to_device_image(pair.deformed)
+    srv = dic.Server(0, max_active=4, hbm_budget_bytes=1e12)
+    r0 = srv.add_reference(ref, roi, **w.params())
+    one = srv.stats()["used_bytes"]
+    t, out = srv.submit(r0, de, w.seeds)
+    with pytest.raises(dic.DicError) as e:     # a waiting request holds it
+        srv.remove_reference(r0)
+    assert e.value.code == dic.DIC_E_STATE
+    while not srv.poll(t)[0]:
+        srv.step(4)
+    torch.cuda.synchronize()
+    first = {k: v.cpu().numpy() for k, v in out.items()}
+    srv.close()
+
+    # a budget for one reference and less than one request's scratch (about a
+    # third of the reference's bytes at this size)
+    srv = dic.Server(0, max_active=4, hbm_budget_bytes=1.2 * one)
+    r0 = srv.add_reference(ref, roi, **w.params())
+    with pytest.raises(dic.DicError) as e:
+        srv.add_reference(ref, roi, **w.params())
+    assert e.value.code == dic.DIC_E_NOMEM
+    t, _ = srv.submit(r0, de, w.seeds)   # needs request scratch beyond the budget
+    srv.step(1)
+    assert srv.poll(t)[:2] == (True, dic.DIC_E_NOMEM)
+    srv.remove_reference(r0)
+    assert srv.stats()["used_bytes"] == 0
+    with pytest.raises(dic.DicError):
+        srv.submit(r0, de, w.seeds)
+    assert srv.poll(t)[0]                 # finished tickets stay pollable
+    srv.close()
+
+    srv = dic.Server(0, max_active=4, hbm_budget_bytes=1e12)
+    r0 = srv.add_reference(ref, roi, **w.params())
+    srv.remove_reference(r0)
+    r1 = srv.add_reference(ref, roi, **w.params())
+    assert r1 != r0
+    t, out = srv.submit(r1, de, w.seeds)
+    while not srv.poll(t)[0]:
+        srv.step(4)
+    torch.cuda.synchronize()
+    _equal({k: v.cpu().numpy() for k, v in out.items()}, first, "re-added")
+    srv.close()
