@@ -387,8 +387,11 @@ def main():
     ap.add_argument("--latency-runs", type=int, default=30, help="plain single-frame calls for p50/p99")
     ap.add_argument("--size", type=int, default=2048)
     ap.add_argument("--fp32-reductions", action="store_true")
-    ap.add_argument("--tps", type=int, default=64, help="threads per subset, batched form")
-    ap.add_argument("--plain-tps", type=int, default=128, help="threads per subset, plain form")
+    ap.add_argument("--tps", type=int, default=0, help="threads per subset, batched form (0: autotuned)")
+    ap.add_argument("--plain-tps", type=int, default=0, help="threads per subset, plain form (0: autotuned)")
+    ap.add_argument("--tile", type=int, default=0, help="LDS window side, batched form (0: autotuned with --tps 0)")
+    ap.add_argument("--plain-tile", type=int, default=0, help="LDS window side, plain form")
+    ap.add_argument("--tune-size", type=int, default=1024, help="side of the autotuner's proxy pair")
     ap.add_argument("--cpu-crop", type=int, default=2048, help="oracle sample window (0 = skip)")
     ap.add_argument("--workload", default="2048", choices=["2048", "gigapixel", "serve"],
                     help="2048: the 2048^2 batched/plain benchmark; gigapixel: the 32768^2 pair, repeated; "
@@ -423,20 +426,42 @@ def main():
     ref, frames, roi = render_frames(w, args.batch)
     print("# inputs rendered in %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
 
+    # ---- launch shapes: the autotuner times every candidate on a smaller pair of
+    # the same workload (same field formula and speckle statistics)
+    tuned = {}
+    if args.tps == 0 or args.plain_tps == 0:
+        from paper_2601_12941_amd import autotune
+        wt = synth.workload("c2", size=args.tune_size)
+        tref, tframes, troi = render_frames(wt, args.batch)
+        proxy = (tref, tframes, troi, wt.seeds)
+        pname = "%d^2 crop of the 2048^2 workload recipe" % args.tune_size
+
+        def log(msg):
+            print("# " + msg, file=sys.stderr, flush=True)
+        for form, b in (("batched", args.batch), ("plain", 1)):
+            if (args.tps if form == "batched" else args.plain_tps) == 0:
+                tuned[form] = autotune.choose(w.N, w.step, w.shape, reduce_fp64=not args.fp32_reductions, batch=b,
+                                              seed_radius=w.seed_radius,
+                                              proxy=proxy, proxy_name=pname, log=log, use_cache=False)
+    tps_b = args.tps or tuned["batched"]["threads_per_subset"]
+    tile_b = args.tile if args.tps else tuned["batched"]["tile_side"]
+    tps_p = args.plain_tps or tuned["plain"]["threads_per_subset"]
+    tile_p = args.plain_tile if args.plain_tps else tuned["plain"]["tile_side"]
+
     dev = torch.device("cuda", 0)
     d_ref = dic.to_device_image(ref)
     d_frames = [dic.to_device_image(f) for f in frames]
     d_roi = torch.from_numpy(roi).to(dev)
     eng = dic.Engine(0)
     prm = w.params()
-    prm.update(reduce_fp64=not args.fp32_reductions, threads_per_subset=args.tps)
+    prm.update(reduce_fp64=not args.fp32_reductions, threads_per_subset=tps_b, tile_side=tile_b)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     eng.set_reference(d_ref, d_roi, **prm)
     torch.cuda.synchronize()
     t_ref = time.perf_counter() - t0
     peng = dic.Engine(0)
-    peng.set_reference(d_ref, d_roi, **{**prm, "threads_per_subset": args.plain_tps})
+    peng.set_reference(d_ref, d_roi, **{**prm, "threads_per_subset": tps_p, "tile_side": tile_p})
     seeds = w.seeds
 
     # ---- batched steps
@@ -506,10 +531,11 @@ def main():
         "config": {"workload": "2048x2048 u16 12-bit speckle, sinusoidal u (lambda 10..300 px), subset 31, step 2, "
                                "affine, batched %d frames per step" % args.batch,
                    "size": args.size, "subset": N, "step": w.step, "nodes": last["nodes"], "active": last["active"],
-                   "frames_per_step": args.batch, "threads_per_subset": last["threads_per_subset"]},
+                   "frames_per_step": args.batch, "threads_per_subset": last["threads_per_subset"],
+                   "tile_side": tile_b},
         "plain": {"value": plain_rate, "unit": "converged subsets/s", "latency_ms_p50": float(np.percentile(lat_ms, 50)),
                   "latency_ms_p99": float(np.percentile(lat_ms, 99)), "runs": args.latency_runs,
-                  "threads_per_subset": args.plain_tps},
+                  "threads_per_subset": tps_p, "tile_side": tile_p},
         "batched_over_plain": value / plain_rate,
         "waves_per_frame": last["waves"],
         "iterations_per_subset": iters / max(1, conv),
@@ -517,6 +543,10 @@ def main():
         "set_reference_ms": t_ref * 1e3,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "autotune": {k: {"threads_per_subset": v["threads_per_subset"], "tile_side": v["tile_side"],
+                         "proxy": v["proxy"],
+                         "candidates": [[r["threads_per_subset"], r["tile_side"], round(r["rate"] / 1e6, 2)]
+                                        for r in v["table"]]} for k, v in tuned.items()},
     }
     print(json.dumps(rec))
     eng.close()

@@ -67,6 +67,7 @@ struct dic_ctx {
     dic_stats stats{};
 
     size_t coef_elems() const { return static_cast<size_t>(cpitch) * (H + 2 * kPad); }
+    int window_side() const { return prm.tile_side ? prm.tile_side : tile_side(prm.subset_size); }
 
     RefView view() const
     {
@@ -93,7 +94,7 @@ struct dic_ctx {
         R.zncc_min = static_cast<float>(prm.zncc_min);
         R.guess_copy = prm.guess_mode;
         R.half = prm.coef_fp16 != 0;
-        R.ts = tile_side(prm.subset_size);
+        R.ts = window_side();
         return R;
     }
 };

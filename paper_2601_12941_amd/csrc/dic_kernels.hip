@@ -181,6 +181,36 @@ __device__ __forceinline__ void block_allreduce(V (&v)[NV], V *red, int &parity)
     }
 }
 
+// Sum of NV values over the T threads of a workgroup, for wavefront 0 only: the
+// same wavefront totals and the same fixed-order sum from LDS as block_allreduce
+// (so the totals agree with it bitwise); the other wavefronts skip the read-back.
+template <int T, int NV, typename V>
+__device__ __forceinline__ void block_reduce_first(V (&v)[NV], V *red, int &parity)
+{
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = wave_allreduce(v[i]);
+    if constexpr (T > 64) {
+        constexpr int NW = T / 64;
+        V *buf = red + parity * NW * NV;
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) buf[w * NV + i] = v[i];
+        }
+        __syncthreads();
+        if (w == 0) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                V acc = buf[i];
+#pragma unroll
+                for (int ww = 1; ww < NW; ++ww) acc += buf[ww * NV + i];
+                v[i] = acc;
+            }
+        }
+        parity ^= 1;
+    }
+}
+
 // Subset pixels over the T threads of a workgroup, column per thread: thread t owns
 // column c = t mod N of the subset and rows r0 + R j (r0 = t div N, R = T div N rows
 // per pass) for j < P; threads t >= N R own nothing.  Offsets from the subset centre:
@@ -938,6 +968,8 @@ __global__ __launch_bounds__(T) void k_wave(const FrameTable frames, int step)
     __shared__ int prefix[kMaxFrames + 1];
     __shared__ int owned[kMaxFrames + 1];
     __shared__ double cache[NC];      // this subset's reference cache
+    __shared__ double pub_p[NP];      // parameters published by the first wavefront
+    __shared__ int pub_stop;
     const int nframes = frames.n;
 
     // Frame affinity: workgroups are placed on the 8 XCDs round-robin by index, so
@@ -947,6 +979,7 @@ __global__ __launch_bounds__(T) void k_wave(const FrameTable frames, int step)
     const int grp = static_cast<int>(blockIdx.x) % G;
     const int gb = static_cast<int>(blockIdx.x) / G, gstride = static_cast<int>(gridDim.x) / G;
     const int t = threadIdx.x;
+    const int wid = t >> 6;   // wavefront index in the workgroup
     if (t == 0) {
         int acc = 0, m = 0;
         for (int f = grp; f < nframes; f += G, ++m) {
@@ -1181,12 +1214,37 @@ __global__ __launch_bounds__(T) void k_wave(const FrameTable frames, int step)
                 float s[NS];
 #pragma unroll
                 for (int i = 0; i < NS; ++i) s[i] = 0.0f;
-                // this thread's column: X, Y at row j are X0 + j XR, Y0 + j YR (affine part)
-                const float X0 = fmaf(A2, dy0, fmaf(A1, dxf, A0)), XR = A2 * dyR;
-                const float Y0 = fmaf(B2, dy0, fmaf(B1, dxf, B0)), YR = B2 * dyR;
+                if (fits) {
+                    // LDS window, branch-free: an entry past this thread's rows samples
+                    // the subset's last row in its column (inside the window) and is
+                    // weighted by zero, so every lane runs the same instruction stream
+                    const float dyl = static_cast<float>(N - 1 - h);
+                    const float Xc = fmaf(A1, dxf, A0), Yc = fmaf(B1, dxf, B0);
+                    const float *tb = tile - ts - 1;
 #pragma unroll
-                for (int j = 0; j < P; ++j) {
-                    if (j < L.jmax) {
+                    for (int j = 0; j < P; ++j) {
+                        const bool on = j < L.jmax;
+                        const float dy = on ? fmaf(static_cast<float>(j), dyR, dy0) : dyl;
+                        float X = fmaf(A2, dy, Xc);
+                        float Y = fmaf(B2, dy, Yc);
+                        if constexpr (NP == 12) {
+                            const float xx = dxf * dxf, xy = dxf * dy, yy = dy * dy;
+                            X = fmaf(Q[2], yy, fmaf(Q[1], xy, fmaf(Q[0], xx, X)));
+                            Y = fmaf(Q[5], yy, fmaf(Q[4], xy, fmaf(Q[3], xx, Y)));
+                        }
+                        const float fx0 = floorf(X), fy0 = floorf(Y);
+                        float wx0, wx1, wx2, wx3, wy0, wy1, wy2, wy3;
+                        bspline_w(X - fx0, wx0, wx1, wx2, wx3);
+                        bspline_w(Y - fy0, wy0, wy1, wy2, wy3);
+                        const int off = static_cast<int>(fy0) * ts + static_cast<int>(fx0);
+                        const float g = interp16(tb + off, ts, wx0, wx1, wx2, wx3, wy0, wy1, wy2, wy3);
+                        accumulate<NP>(s, on ? g - fm32 : 0.0f, fb[j], gx[j], gy[j], dxf, dy);
+                    }
+                } else {
+                    // taps straight from global memory (a window that does not fit)
+                    const float X0 = fmaf(A2, dy0, fmaf(A1, dxf, A0)), XR = A2 * dyR;
+                    const float Y0 = fmaf(B2, dy0, fmaf(B1, dxf, B0)), YR = B2 * dyR;
+                    for (int j = 0; j < L.jmax; ++j) {
                         const float dx = dxf, dy = fmaf(static_cast<float>(j), dyR, dy0);
                         float X = fmaf(static_cast<float>(j), XR, X0);
                         float Y = fmaf(static_cast<float>(j), YR, Y0);
@@ -1200,86 +1258,113 @@ __global__ __launch_bounds__(T) void k_wave(const FrameTable frames, int step)
                         bspline_w(X - fx0, wx0, wx1, wx2, wx3);
                         bspline_w(Y - fy0, wy0, wy1, wy2, wy3);
                         const int ixl = static_cast<int>(fx0) - 1, iyl = static_cast<int>(fy0) - 1;
+                        const int64_t go = static_cast<int64_t>(oy + iyl) * F.dpitch + (ox + ixl);
                         float g;
-                        if (fits) {
-                            g = interp16(tile + iyl * ts + ixl, ts, wx0, wx1, wx2, wx3, wy0, wy1, wy2, wy3);
-                        } else {
-                            const int64_t go = static_cast<int64_t>(oy + iyl) * F.dpitch + (ox + ixl);
-                            if (half)
-                                g = interp16(static_cast<const __half *>(F.dcoef) + go, F.dpitch, wx0, wx1, wx2, wx3,
-                                             wy0, wy1, wy2, wy3);
-                            else
-                                g = interp16(static_cast<const float *>(F.dcoef) + go, F.dpitch, wx0, wx1, wx2, wx3,
-                                             wy0, wy1, wy2, wy3);
-                        }
-                        accumulate<NP>(s, g - fm32, fb[j], gx[j], gy[j], dx, dy);
+                        if (half)
+                            g = interp16(static_cast<const __half *>(F.dcoef) + go, F.dpitch, wx0, wx1, wx2, wx3, wy0,
+                                         wy1, wy2, wy3);
+                        else
+                            g = interp16(static_cast<const float *>(F.dcoef) + go, F.dpitch, wx0, wx1, wx2, wx3, wy0,
+                                         wy1, wy2, wy3);
+                        float fbj = 0.0f, gxj = 0.0f, gyj = 0.0f;
+#pragma unroll
+                        for (int q = 0; q < P; ++q)
+                            if (q == j) {
+                                fbj = fb[q];
+                                gxj = gx[q];
+                                gyj = gy[q];
+                            }
+                        accumulate<NP>(s, g - fm32, fbj, gxj, gyj, dx, dy);
                     }
                 }
-                // ---- reduce and solve
+                // ---- reduce; the rest of the iteration (checks, increment, composition,
+                // convergence) is scalar FP64 work that the first wavefront does alone and
+                // publishes through LDS, so the other wavefronts do not repeat it
                 Acc v[NS];
 #pragma unroll
                 for (int i = 0; i < NS; ++i) v[i] = static_cast<Acc>(s[i]);
-                block_allreduce<T, NS>(v, red, parity);
-                const Acc S0 = v[0], S1 = v[1];
-                const Acc gm = S0 * static_cast<Acc>(inv_n);
-                const Acc dg2 = S1 - S0 * gm;
-                if (isnan(static_cast<double>(dg2))) { status = kNan; break; }
-                const double lev = fmax(1.0, fabs(cache[0] + static_cast<double>(gm)));
-                if (static_cast<double>(dg2) <= n * (kFlatRel * lev) * (kFlatRel * lev)) {
-                    status = kFlatDef;
-                    zncc_out = 0.0f;
-                    break;
-                }
-                // The sums cancel in FP64 (or FP32); the ratio df/dg and the ZNCC need only
-                // FP32 accuracy: an FP32 ratio moves b by ~1e-7 of |sum J fbar|, i.e. the
-                // increment by ~1e-8 px.  Equal reference and deformed sums give ratio 1
-                // and ZNCC 1 exactly.
-                const Acc sfg = v[2] - gm * static_cast<Acc>(cache[2]);
-                const float ratio_f = sqrtf(static_cast<float>(cache[1]) / static_cast<float>(dg2));
-                const float zn = static_cast<float>(sfg) / (static_cast<float>(dg2) * ratio_f);
-                const Acc ratio = static_cast<Acc>(ratio_f);
-                Acc b[NP];
-#pragma unroll
-                for (int a = 0; a < NP; ++a)
-                    b[a] = static_cast<Acc>(cache[3 + NP + a]) - ratio * (v[3 + a] - gm * static_cast<Acc>(cache[3 + a]));
-                double dp[NP];
-                {
-                    int q = 0;
-                    Acc acc[NP];
-#pragma unroll
-                    for (int a = 0; a < NP; ++a) acc[a] = 0;
-#pragma unroll
-                    for (int a = 0; a < NP; ++a)
-#pragma unroll
-                        for (int c = a; c < NP; ++c) {
-                            const Acc hv = static_cast<Acc>(cache[3 + 2 * NP + q]);
-                            ++q;
-                            acc[a] += hv * b[c];
-                            if (c != a) acc[c] += hv * b[a];
+                block_reduce_first<T, NS>(v, red, parity);
+                int stop = 0;
+                if (wid == 0) {
+                    do {
+                        const Acc S0 = v[0], S1 = v[1];
+                        const Acc gm = S0 * static_cast<Acc>(inv_n);
+                        const Acc dg2 = S1 - S0 * gm;
+                        if (isnan(static_cast<double>(dg2))) { status = kNan; stop = 1; break; }
+                        const double lev = fmax(1.0, fabs(cache[0] + static_cast<double>(gm)));
+                        if (static_cast<double>(dg2) <= n * (kFlatRel * lev) * (kFlatRel * lev)) {
+                            status = kFlatDef;
+                            zncc_out = 0.0f;
+                            stop = 1;
+                            break;
                         }
+                        // The sums cancel in FP64 (or FP32); the ratio df/dg and the ZNCC need
+                        // only FP32 accuracy: an FP32 ratio moves b by ~1e-7 of |sum J fbar|,
+                        // i.e. the increment by ~1e-8 px.  Equal reference and deformed sums
+                        // give ratio 1 and ZNCC 1 exactly.
+                        const Acc sfg = v[2] - gm * static_cast<Acc>(cache[2]);
+                        const float ratio_f = sqrtf(static_cast<float>(cache[1]) / static_cast<float>(dg2));
+                        const float zn = static_cast<float>(sfg) / (static_cast<float>(dg2) * ratio_f);
+                        const Acc ratio = static_cast<Acc>(ratio_f);
+                        Acc b[NP];
 #pragma unroll
-                    for (int a = 0; a < NP; ++a) dp[a] = -static_cast<double>(acc[a]);
+                        for (int a = 0; a < NP; ++a)
+                            b[a] = static_cast<Acc>(cache[3 + NP + a]) -
+                                   ratio * (v[3 + a] - gm * static_cast<Acc>(cache[3 + a]));
+                        double dp[NP];
+                        {
+                            int q = 0;
+                            Acc acc[NP];
+#pragma unroll
+                            for (int a = 0; a < NP; ++a) acc[a] = 0;
+#pragma unroll
+                            for (int a = 0; a < NP; ++a)
+#pragma unroll
+                                for (int c = a; c < NP; ++c) {
+                                    const Acc hv = static_cast<Acc>(cache[3 + 2 * NP + q]);
+                                    ++q;
+                                    acc[a] += hv * b[c];
+                                    if (c != a) acc[c] += hv * b[a];
+                                }
+#pragma unroll
+                            for (int a = 0; a < NP; ++a) dp[a] = -static_cast<double>(acc[a]);
+                        }
+                        zncc_out = zn;
+                        if constexpr (NP == 6) compose_affine(p, dp);
+                        else compose_quadratic(p, dp);
+                        double nrm = dp[0] * dp[0] + dp[1] * dp[1];
+                        {
+                            double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+                            for (int a = 2; a < 6; ++a) s1 += dp[a] * dp[a];
+#pragma unroll
+                            for (int a = 6; a < NP; ++a) s2 += dp[a] * dp[a];
+                            nrm += hd * hd * s1 + hd * hd * hd * hd * s2;
+                        }
+                        bool bad = isnan(zn) || isnan(nrm);
+#pragma unroll
+                        for (int a = 0; a < NP; ++a) bad = bad || isnan(p[a]);
+                        if (bad) { status = kNan; stop = 1; break; }
+                        if (nrm < R.tol2) {
+                            status = zncc_out >= R.zncc_min ? kConverged : kLowZncc;
+                            stop = 1;
+                        }
+                    } while (false);
                 }
-                zncc_out = zn;
-                if constexpr (NP == 6) compose_affine(p, dp);
-                else compose_quadratic(p, dp);
-                double nrm = dp[0] * dp[0] + dp[1] * dp[1];
-                {
-                    double s1 = 0.0, s2 = 0.0;
+                if constexpr (T > 64) {
+                    if (t == 0) {
 #pragma unroll
-                    for (int a = 2; a < 6; ++a) s1 += dp[a] * dp[a];
+                        for (int a = 0; a < NP; ++a) pub_p[a] = p[a];
+                        pub_stop = stop;
+                    }
+                    __syncthreads();
+                    if (wid != 0) {
 #pragma unroll
-                    for (int a = 6; a < NP; ++a) s2 += dp[a] * dp[a];
-                    nrm += hd * hd * s1 + hd * hd * hd * hd * s2;
+                        for (int a = 0; a < NP; ++a) p[a] = pub_p[a];
+                        stop = pub_stop;
+                    }
                 }
-                bool bad = isnan(zn) || isnan(nrm);
-#pragma unroll
-                for (int a = 0; a < NP; ++a) bad = bad || isnan(p[a]);
-                if (bad) { status = kNan; break; }
-                if (nrm < R.tol2) {
-                    status = zncc_out >= R.zncc_min ? kConverged : kLowZncc;
-                    break;
-                }
+                if (stop) break;
             }
         }
 

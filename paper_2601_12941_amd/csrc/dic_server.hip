@@ -459,7 +459,7 @@ dic_status dic_server_step(dic_server *s, int32_t steps)
                 for (size_t i = i0; i < i1; ++i) {
                     table.f[i - i0] = reqs[i]->F;
                     nmax = std::max(nmax, reqs[i]->ref->prm.subset_size);
-                    tsmax = std::max(tsmax, tile_side(reqs[i]->ref->prm.subset_size));
+                    tsmax = std::max(tsmax, reqs[i]->ref->window_side());
                 }
                 table.n = static_cast<int>(i1 - i0);
                 const int np = std::get<0>(g.first), tps = std::get<1>(g.first);

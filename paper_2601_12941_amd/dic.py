@@ -44,7 +44,7 @@ class DicParams(C.Structure):
     _fields_ = [("subset_size", C.c_int32), ("step", C.c_int32), ("shape", C.c_int32), ("max_iter", C.c_int32),
                 ("tol", C.c_double), ("zncc_min", C.c_double), ("seed_radius", C.c_int32),
                 ("guess_mode", C.c_int32), ("coef_fp16", C.c_int32), ("reduce_fp64", C.c_int32),
-                ("nan_unconverged", C.c_int32), ("threads_per_subset", C.c_int32)]
+                ("nan_unconverged", C.c_int32), ("threads_per_subset", C.c_int32), ("tile_side", C.c_int32)]
 
 
 class DicSeed(C.Structure):
@@ -84,6 +84,12 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError("the HIP library %s is not built; run paper_2601_12941_amd.build.build()" % path)
+    # PyTorch ships its own HIP runtime under another file name; loading it first
+    # makes the library bind to that same runtime instead of a second copy
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(path)
     P = C.POINTER
     L.dic_create.argtypes = [P(C.c_void_p), C.c_int, C.c_void_p]
@@ -283,10 +289,10 @@ class Engine:
 
     def set_reference(self, ref, roi=None, *, subset_size, step, shape=6, tol=1e-4, max_iter=50, zncc_min=0.7,
                       seed_radius=8, guess="extrapolate", coef_fp16=False, reduce_fp64=True, nan_unconverged=False,
-                      threads_per_subset=0):
+                      threads_per_subset=0, tile_side=0):
         prm = DicParams(subset_size, step, shape, max_iter, tol, zncc_min, seed_radius,
                         1 if guess == "copy" else 0, int(bool(coef_fp16)), int(bool(reduce_fp64)),
-                        int(bool(nan_unconverged)), threads_per_subset)
+                        int(bool(nan_unconverged)), threads_per_subset, tile_side)
         roi_ptr = 0
         if roi is not None:
             import torch
@@ -342,9 +348,11 @@ class Engine:
 
 
 def _params(subset_size, step, shape=6, tol=1e-4, max_iter=50, zncc_min=0.7, seed_radius=8, guess="extrapolate",
-            coef_fp16=False, reduce_fp64=True, nan_unconverged=False, threads_per_subset=0) -> DicParams:
+            coef_fp16=False, reduce_fp64=True, nan_unconverged=False, threads_per_subset=0,
+            tile_side=0) -> DicParams:
     return DicParams(subset_size, step, shape, max_iter, tol, zncc_min, seed_radius, 1 if guess == "copy" else 0,
-                     int(bool(coef_fp16)), int(bool(reduce_fp64)), int(bool(nan_unconverged)), threads_per_subset)
+                     int(bool(coef_fp16)), int(bool(reduce_fp64)), int(bool(nan_unconverged)), threads_per_subset,
+                     tile_side)
 
 
 def _roi_ptr(roi, ref) -> int:

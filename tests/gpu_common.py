@@ -33,7 +33,7 @@ def gpu_run(pair, w, engine=None, **over):
 def oracle_run(pair, w, **over):
     prm = dict(w.params())
     prm.update(over)
-    for k in ("coef_fp16", "reduce_fp64", "threads_per_subset", "nan_unconverged"):
+    for k in ("coef_fp16", "reduce_fp64", "threads_per_subset", "nan_unconverged", "tile_side"):
         prm.pop(k, None)
     return oracle.correlate(pair.ref, pair.deformed, pair.roi, seeds=w.seeds, threads=8, **prm)
 

@@ -49,6 +49,7 @@ int main(void) {
   F(dic_params, subset_size) F(dic_params, step) F(dic_params, shape) F(dic_params, max_iter) F(dic_params, tol)
   F(dic_params, zncc_min) F(dic_params, seed_radius) F(dic_params, guess_mode) F(dic_params, coef_fp16)
   F(dic_params, reduce_fp64) F(dic_params, nan_unconverged) F(dic_params, threads_per_subset)
+  F(dic_params, tile_side)
   printf("dic_seed %zu\n", sizeof(dic_seed));
   printf("dic_result %zu\n", sizeof(dic_result));
   F(dic_result, p) F(dic_result, zncc) F(dic_result, iters) F(dic_result, status) F(dic_result, wave)
