@@ -79,6 +79,95 @@ def profiled_traffic():
     return rec["traffic_bytes_per_launch"] if rec.get("source_sha256") == sha else None
 
 
+PROFILE_BENCH = "bench.py --steps 2 --warmup 1 --latency-runs 3 --cpu-crop 0 --tps 64 --tile 48 --plain-tps 128 --plain-tile 48"
+PMC_BENCH = "bench.py --steps 1 --warmup 0 --latency-runs 1 --cpu-crop 0 --tps 64 --tile 48 --plain-tps 128 --plain-tile 48"
+
+
+def _short(name):
+    name = name.replace("dicmi::", "").replace("void ", "")
+    return name.split("(")[0]
+
+
+def summarize_trace(d, out):
+    """profiles/*.md from a rocprofv3 --kernel-trace --stats directory."""
+    import csv
+    import hashlib
+    stats = next(os.path.join(r, f) for r, _, fs in os.walk(d) for f in fs if f.endswith("kernel_stats.csv"))
+    rows = list(csv.DictReader(open(stats)))
+    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2601_12941_amd", "csrc", "dic_kernels.hip"), "rb").read())
+    lines = ["# k_wave on the 2048^2 workload: rocprofv3 kernel trace", "",
+             "Command (from the repository root on the MI355X box; rocprofv3 run from /tmp with TMPDIR=/tmp):", "",
+             "```", "rocprofv3 --kernel-trace --stats -f csv -d <out> -o run -- python3 " + PROFILE_BENCH, "```", "",
+             "Summary written by `python bench.py --summarize-trace <out> --summary-out <this file>`.", "",
+             "Workload: 2048x2048 u16 speckle, sinusoidal u, subset 31, step 2, affine (1 010 025 active subsets per "
+             "frame, 1005 waves). Batched form: 16 frames per launch, 64 threads per subset, 48-sample window "
+             "(`k_wave<6, 64, 16, true>`); plain form: one frame per call, 128 threads per subset "
+             "(`k_wave<6, 128, 8, true>`); the launch shapes the autotuner picks on this workload.", "",
+             "| Kernel | Calls | Total ms | Average us | % | Min us | Max us |", "|---|---|---|---|---|---|---|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:14]:
+        lines.append("| `%s` | %s | %.1f | %.1f | %.2f | %.1f | %.1f |" % (
+            _short(r["Name"]), r["Calls"], float(r["TotalDurationNs"]) / 1e6, float(r["AverageNs"]) / 1e3,
+            float(r["Percentage"]), float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3))
+    lines += ["", "The batched-form k_wave average above is the launch duration `bench.py` measures live with HIP events "
+              "(`roofline.avg_launch_us`; the live figure spans back-to-back launches, so it includes the few-microsecond "
+              "gaps between them).",
+              "Kernel source at the time of this profile: sha256 `%s` of `paper_2601_12941_amd/csrc/dic_kernels.hip`."
+              % sha.hexdigest()]
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("wrote", out)
+
+
+def summarize_pmc(fetch_dir, write_dir, cfetch_dir, cwrite_dir, out_md, out_json):
+    """HBM byte counters per dispatch, scaled by what the same counters read for a
+    256 MiB device copy; writes the summary table and the per-launch traffic of
+    the batched k_wave that bench.py reports."""
+    import csv
+    import hashlib
+
+    def per_kernel(d, counter):
+        f = next(os.path.join(r, x) for r, _, fs in os.walk(d) for x in fs if x.endswith("counter_collection.csv"))
+        acc, disp = {}, {}
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] != counter:
+                continue
+            k = _short(r["Kernel_Name"])
+            acc[k] = acc.get(k, 0.0) + float(r["Counter_Value"])
+            disp.setdefault(k, set()).add(r["Dispatch_Id"])
+        return {k: (acc[k] / len(disp[k]), len(disp[k])) for k in acc}
+    copy_bytes = 256 * (1 << 20)
+    cf = max(per_kernel(cfetch_dir, "FETCH_SIZE").values(), key=lambda v: v[0])[0]
+    cw = max(per_kernel(cwrite_dir, "WRITE_SIZE").values(), key=lambda v: v[0])[0]
+    ff, wf = copy_bytes / 1024.0 / cf, copy_bytes / 1024.0 / cw
+    fe, wr = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
+    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2601_12941_amd", "csrc", "dic_kernels.hip"), "rb").read())
+    lines = ["# k_wave on the 2048^2 workload: HBM-side byte counters", "",
+             "Commands (each a separate pass; rocprofv3 run from /tmp with TMPDIR=/tmp):", "", "```",
+             "rocprofv3 --pmc FETCH_SIZE -f csv -d <fetch> -o run -- python3 " + PMC_BENCH,
+             "rocprofv3 --pmc WRITE_SIZE -f csv -d <write> -o run -- python3 " + PMC_BENCH,
+             "rocprofv3 --pmc FETCH_SIZE -f csv -d <copy_fetch> -o run -- python3 bench.py --copy-probe",
+             "rocprofv3 --pmc WRITE_SIZE -f csv -d <copy_write> -o run -- python3 bench.py --copy-probe", "```", "",
+             "Summary written by `python bench.py --summarize-pmc <fetch> <write> <copy_fetch> <copy_write>`.", "",
+             "Calibration: a 256 MiB device copy reads FETCH_SIZE %.1f KiB and WRITE_SIZE %.1f KiB per dispatch "
+             "(exact: 262144 KiB), so FETCH_SIZE is scaled by %.4f and WRITE_SIZE by %.4f." % (cf, cw, ff, wf), "",
+             "| Kernel | Dispatches | FETCH_SIZE KiB/dispatch | scaled fetch MB/dispatch | WRITE_SIZE KiB/dispatch | "
+             "scaled write MB/dispatch |", "|---|---|---|---|---|---|"]
+    for k in sorted(fe, key=lambda k: -fe[k][0] * fe[k][1])[:10]:
+        w = wr.get(k, (0.0, 0))[0]
+        lines.append("| `%s` | %d | %.1f | %.2f | %.1f | %.2f |" % (k, fe[k][1], fe[k][0], fe[k][0] * 1024 * ff / 1e6,
+                                                                    w, w * 1024 * wf / 1e6))
+    kb = "k_wave<6, 64, 16, true>"
+    fetch_b = fe[kb][0] * 1024 * ff
+    write_b = wr[kb][0] * 1024 * wf
+    lines += ["", "Kernel source at the time of these counters: sha256 `%s`." % sha.hexdigest()]
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    json.dump({"kernel": kb + " (batched form, 16 frames per launch)", "source_sha256": sha.hexdigest(),
+               "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
+               "traffic_bytes_per_launch": fetch_b + write_b, "dispatches": fe[kb][1],
+               "copy_calibration": {"bytes": copy_bytes, "fetch_kib": cf, "write_kib": cw, "fetch_factor": ff,
+                                    "write_factor": wf}}, open(out_json, "w"), indent=1)
+    print("wrote", out_md, out_json)
+
+
 def copy_probe(mib=256, reps=3):
     """A device-to-device copy of known size: its FETCH_SIZE / WRITE_SIZE counters
     read `mib` MiB each per dispatch on an exact counter."""
@@ -176,6 +265,61 @@ def gigapixel(args, repeats=6, samples=24):
     eng.close()
 
 
+def precision(args):
+    """Precision sweep on the 4096^2-recipe u8 pair with the quadratic field and
+    2 % strain, drawn at --precision-size: subsets 21 and 41 (step 4), affine and
+    quadratic shape functions, FP32- and FP16-stored deformed coefficients (FP32
+    interpolation, FP64 reductions and solve), each compared node by node with
+    the FP64 oracle run in the same wave order, and with the ground truth."""
+    import torch
+    import oracle
+    from paper_2601_12941_amd import dic, synth
+
+    size = args.precision_size
+    w0 = synth.workload("c3", size=size)
+    pair = w0.pair()
+    d_ref = dic.to_device_image(pair.ref)
+    d_def = dic.to_device_image(pair.deformed)
+    d_roi = torch.from_numpy(pair.roi).cuda()
+    rows = []
+    for N in (21, 41):
+        for shape in (6, 12):
+            w = synth.workload("c3", size=size, N=N, shape=shape)
+            t0 = time.perf_counter()
+            o = oracle.correlate(pair.ref, pair.deformed, pair.roi, seeds=w.seeds, threads=16,
+                                 **{k: v for k, v in w.params().items()})
+            t_or = time.perf_counter() - t0
+            print("# oracle N%d shape %d: %.1f s" % (N, shape, t_or), file=sys.stderr, flush=True)
+            u, v, _ = synth.truth_at_nodes(pair.field, size, size, N, w.step)
+            for fp16 in (False, True):
+                eng = dic.Engine(0)
+                eng.set_reference(d_ref, d_roi, **w.params(), coef_fp16=fp16)
+                out = eng.correlate(d_def, w.seeds)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                out = eng.correlate(d_def, w.seeds)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t1) * 1e3
+                g = {k: t.cpu().numpy() for k, t in out.items()}
+                eng.close()
+                act = o["status"] != oracle.ST["NOT_IN_ROI"]
+                both = (g["status"] == 0) & (o["status"] == 0)
+                duv = np.maximum(np.abs(g["p"][0] - o["p"][0]), np.abs(g["p"][1] - o["p"][1]))[both]
+                dz = np.abs(g["zncc"] - o["zncc"])[both]
+                et = np.hypot(g["p"][0] - u, g["p"][1] - v)[g["status"] == 0]
+                rows.append({"subset": N, "shape": "quadratic" if shape == 12 else "affine",
+                             "coefficients": "fp16" if fp16 else "fp32", "nodes_compared": int(both.sum()),
+                             "max_duv_px": float(duv.max()), "rms_duv_px": float(np.sqrt((duv ** 2).mean())),
+                             "p999_duv_px": float(np.percentile(duv, 99.9)), "max_dzncc": float(dz.max()),
+                             "status_mismatch": float((g["status"] != o["status"])[act].mean()),
+                             "vs_truth_rms_px": float(np.sqrt((et ** 2).mean())), "vs_truth_max_px": float(et.max()),
+                             "gpu_ms": ms, "oracle_s": t_or})
+                print("# " + json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    print(json.dumps({"workload": "precision sweep: %d^2 u8 speckle, u = 1e-5 x^2 + 0.3 + 0.02 x, "
+                                  "v = -2e-5 xy + 0.2 + 0.02 y about the centre, step 4" % size,
+                      "reductions": "fp64", "rows": rows}))
+
+
 def serve(args):
     """The serving mix: 8 resident 4096^2 u8 references; requests arrive as a
     Poisson process (rate per second, fixed duration) and each correlates a
@@ -223,8 +367,18 @@ def serve(args):
         o = synth.serve_window(S)
         return d_refs[r][o:o + S, o:o + S]
 
+    # launch shapes per subset size, tuned for many requests in flight (batch 16)
+    from paper_2601_12941_amd import autotune
+    shapes = {}
+    for N in synth.SERVE_SUBSETS:
+        ch = autotune.choose(N, 2, batch=16, size=1024, seed_radius=8, use_cache=False,
+                             log=lambda m: print("# " + m, file=sys.stderr, flush=True))
+        shapes[N] = (ch["threads_per_subset"], ch["tile_side"])
+    note("launch shapes tuned: %s" % shapes)
+
     def params(N, st):
-        return dict(subset_size=N, step=st, shape=6, tol=1e-4, max_iter=50, zncc_min=0.7, seed_radius=8)
+        return dict(subset_size=N, step=st, shape=6, tol=1e-4, max_iter=50, zncc_min=0.7, seed_radius=8,
+                    threads_per_subset=shapes[N][0], tile_side=shapes[N][1])
 
     srv = dic.Server(0, max_active=args.max_active, hbm_budget_bytes=args.budget_gb * 1e9)
     # warm-up: every kernel shape once on a 256^2 request, outside the clock
@@ -343,7 +497,9 @@ def serve(args):
         o = synth.serve_window(q.S)
         refw = refs[q.ref][o:o + q.S, o:o + q.S]
         r = oracle.correlate(np.ascontiguousarray(refw), host_frames[i], synth.serve_roi(q.S),
-                             seeds=[(q.S / 2.0, q.S / 2.0, 0.0, 0.0)], threads=16, **params(q.N, q.step))
+                             seeds=[(q.S / 2.0, q.S / 2.0, 0.0, 0.0)], threads=16,
+                             **{k: v for k, v in params(q.N, q.step).items()
+                                if k not in ("threads_per_subset", "tile_side")})
         g = kept[i]
         both = (g["status"] == 0) & (r["status"] == 0)
         act = r["status"] != oracle.ST["NOT_IN_ROI"]
@@ -371,6 +527,7 @@ def serve(args):
            "keeps_up": bool(t_end - last_arrival < 2.0),
            "queue_per_second": {"columns": ["t_s", "queued", "active", "resident_refs", "used_gb"], "rows": qlog},
            "registrations": reg["count"], "registration_ms_total": reg["ms"], "evictions": reg["evictions"],
+           "launch_shapes": {str(N): {"threads_per_subset": v[0], "tile_side": v[1]} for N, v in shapes.items()},
            "sampled_parity": {"requests": len(kept), "max_duv_px": max(errs) if errs else None,
                               "max_dzncc": max(dz) if dz else None, "min_status_agree": min(agree) if agree else None},
            "error_vs_truth_rms_px_max_over_sample": max(terr) if terr else None}
@@ -393,18 +550,30 @@ def main():
     ap.add_argument("--plain-tile", type=int, default=0, help="LDS window side, plain form")
     ap.add_argument("--tune-size", type=int, default=1024, help="side of the autotuner's proxy pair")
     ap.add_argument("--cpu-crop", type=int, default=2048, help="oracle sample window (0 = skip)")
-    ap.add_argument("--workload", default="2048", choices=["2048", "gigapixel", "serve"],
+    ap.add_argument("--workload", default="2048", choices=["2048", "gigapixel", "serve", "precision"],
                     help="2048: the 2048^2 batched/plain benchmark; gigapixel: the 32768^2 pair, repeated; "
                          "serve: the serving mix")
+    ap.add_argument("--precision-size", type=int, default=2048, help="precision: image side")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: seconds of Poisson arrivals")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: requests per second")
     ap.add_argument("--max-active", type=int, default=48, help="serve: requests on the device at once")
     ap.add_argument("--budget-gb", type=float, default=170.0, help="serve: library HBM budget")
     ap.add_argument("--chunk", type=int, default=8, help="serve: launch steps per server call")
     ap.add_argument("--parity-samples", type=int, default=8, help="serve: requests checked against the oracle")
+    ap.add_argument("--summarize-trace", metavar="DIR", help="write the kernel-trace summary of a rocprofv3 run")
+    ap.add_argument("--summary-out", default=os.path.join(ROOT, "profiles", "k_wave_2048_kernel_trace.md"))
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="write the HBM counter summary and per-launch traffic from four rocprofv3 --pmc runs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.summary_out)
+        return
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc, os.path.join(ROOT, "profiles", "k_wave_2048_hbm_counters.md"),
+                      os.path.join(ROOT, "profiles", "k_wave_2048_batched_traffic.json"))
+        return
     if args.copy_probe:
         copy_probe()
         return
@@ -413,6 +582,9 @@ def main():
         sys.exit(2)
     if args.workload == "serve":
         serve(args)
+        return
+    if args.workload == "precision":
+        precision(args)
         return
     if args.workload == "gigapixel":
         gigapixel(args)

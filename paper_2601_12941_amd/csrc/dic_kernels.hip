@@ -866,6 +866,8 @@ void launch_finalize(const RefView &R, const FrameState &F, int np, bool nan_unc
 // p_j - dp_j (no "(1 + small) - 1" cancellation; exact when dp = 0).
 __device__ __forceinline__ void compose_affine(double (&p)[6], const double (&d)[6])
 {
+    // contraction is free here: d = 0 leaves p unchanged with or without it
+#pragma clang fp contract(fast)
     const double a = 1.0 + d[2], b = d[3], c = d[4], e = 1.0 + d[5];
     const double det = a * e - b * c;
     // the reciprocal scales terms that are differences of order |dp|: FP32 suffices
@@ -1221,24 +1223,29 @@ __global__ __launch_bounds__(T) void k_wave(const FrameTable frames, int step)
                     const float dyl = static_cast<float>(N - 1 - h);
                     const float Xc = fmaf(A1, dxf, A0), Yc = fmaf(B1, dxf, B0);
                     const float *tb = tile - ts - 1;
+                    // rows per thread of this subset (a launch may mix subset sizes, P is
+                    // the largest); uniform across the workgroup
+                    const int JM = __builtin_amdgcn_readfirstlane((N + L.R - 1) / L.R);
 #pragma unroll
                     for (int j = 0; j < P; ++j) {
-                        const bool on = j < L.jmax;
-                        const float dy = on ? fmaf(static_cast<float>(j), dyR, dy0) : dyl;
-                        float X = fmaf(A2, dy, Xc);
-                        float Y = fmaf(B2, dy, Yc);
-                        if constexpr (NP == 12) {
-                            const float xx = dxf * dxf, xy = dxf * dy, yy = dy * dy;
-                            X = fmaf(Q[2], yy, fmaf(Q[1], xy, fmaf(Q[0], xx, X)));
-                            Y = fmaf(Q[5], yy, fmaf(Q[4], xy, fmaf(Q[3], xx, Y)));
+                        if (j < JM) {
+                            const bool on = j < L.jmax;
+                            const float dy = on ? fmaf(static_cast<float>(j), dyR, dy0) : dyl;
+                            float X = fmaf(A2, dy, Xc);
+                            float Y = fmaf(B2, dy, Yc);
+                            if constexpr (NP == 12) {
+                                const float xx = dxf * dxf, xy = dxf * dy, yy = dy * dy;
+                                X = fmaf(Q[2], yy, fmaf(Q[1], xy, fmaf(Q[0], xx, X)));
+                                Y = fmaf(Q[5], yy, fmaf(Q[4], xy, fmaf(Q[3], xx, Y)));
+                            }
+                            const float fx0 = floorf(X), fy0 = floorf(Y);
+                            float wx0, wx1, wx2, wx3, wy0, wy1, wy2, wy3;
+                            bspline_w(X - fx0, wx0, wx1, wx2, wx3);
+                            bspline_w(Y - fy0, wy0, wy1, wy2, wy3);
+                            const int off = static_cast<int>(fy0) * ts + static_cast<int>(fx0);
+                            const float g = interp16(tb + off, ts, wx0, wx1, wx2, wx3, wy0, wy1, wy2, wy3);
+                            accumulate<NP>(s, on ? g - fm32 : 0.0f, fb[j], gx[j], gy[j], dxf, dy);
                         }
-                        const float fx0 = floorf(X), fy0 = floorf(Y);
-                        float wx0, wx1, wx2, wx3, wy0, wy1, wy2, wy3;
-                        bspline_w(X - fx0, wx0, wx1, wx2, wx3);
-                        bspline_w(Y - fy0, wy0, wy1, wy2, wy3);
-                        const int off = static_cast<int>(fy0) * ts + static_cast<int>(fx0);
-                        const float g = interp16(tb + off, ts, wx0, wx1, wx2, wx3, wy0, wy1, wy2, wy3);
-                        accumulate<NP>(s, on ? g - fm32 : 0.0f, fb[j], gx[j], gy[j], dxf, dy);
                     }
                 } else {
                     // taps straight from global memory (a window that does not fit)
@@ -1311,6 +1318,11 @@ __global__ __launch_bounds__(T) void k_wave(const FrameTable frames, int step)
                         for (int a = 0; a < NP; ++a)
                             b[a] = static_cast<Acc>(cache[3 + NP + a]) -
                                    ratio * (v[3 + a] - gm * static_cast<Acc>(cache[3 + a]));
+                        // up to b, the same expressions as the reference precompute (an
+                        // identical subset gives b = 0 exactly); from here on FP64 contraction
+                        // is allowed, since b = 0 still gives a zero increment and unchanged p
+                        {
+#pragma clang fp contract(fast)
                         double dp[NP];
                         {
                             int q = 0;
@@ -1348,6 +1360,7 @@ __global__ __launch_bounds__(T) void k_wave(const FrameTable frames, int step)
                         if (nrm < R.tol2) {
                             status = zncc_out >= R.zncc_min ? kConverged : kLowZncc;
                             stop = 1;
+                        }
                         }
                     } while (false);
                 }
