@@ -310,6 +310,7 @@ def precision(args):
                 rows.append({"subset": N, "shape": "quadratic" if shape == 12 else "affine",
                              "coefficients": "fp16" if fp16 else "fp32", "nodes_compared": int(both.sum()),
                              "max_duv_px": float(duv.max()), "rms_duv_px": float(np.sqrt((duv ** 2).mean())),
+                             "nodes_over_1e-3_px": int((duv > 1e-3).sum()),
                              "p999_duv_px": float(np.percentile(duv, 99.9)), "max_dzncc": float(dz.max()),
                              "status_mismatch": float((g["status"] != o["status"])[act].mean()),
                              "vs_truth_rms_px": float(np.sqrt((et ** 2).mean())), "vs_truth_max_px": float(et.max()),
