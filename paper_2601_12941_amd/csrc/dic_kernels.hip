@@ -791,29 +791,37 @@ __global__ void k_finalize(RefView R, FrameState F, int np)
 // and IC-GN iterations; one atomic per block and counter.
 __global__ __launch_bounds__(256) void k_frame_stats(RefView R, FrameState F)
 {
-    unsigned long long a = 0, b = 0, c = 0;
+    // stat[0] computed nodes, [1] converged, [2] iterations, [3] waves (largest wave index + 1)
+    unsigned long long a = 0, b = 0, c = 0, d = 0;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < R.nodes;
          i += static_cast<int64_t>(gridDim.x) * 256) {
-        a += F.wave[i] >= 0 ? 1 : 0;
+        const int wv = F.wave[i];
+        a += wv >= 0 ? 1 : 0;
         b += F.status[i] == kConverged ? 1 : 0;
         c += static_cast<unsigned long long>(F.iters[i]);
+        d = max(d, static_cast<unsigned long long>(wv + 1));
     }
     for (int m = 1; m < 64; m <<= 1) {
         a += __shfl_xor(a, m);
         b += __shfl_xor(b, m);
         c += __shfl_xor(c, m);
+        d = max(d, __shfl_xor(d, m));
     }
-    __shared__ unsigned long long part[4][3];
+    __shared__ unsigned long long part[4][4];
     if ((threadIdx.x & 63) == 0) {
         part[threadIdx.x >> 6][0] = a;
         part[threadIdx.x >> 6][1] = b;
         part[threadIdx.x >> 6][2] = c;
+        part[threadIdx.x >> 6][3] = d;
     }
     __syncthreads();
     if (threadIdx.x < 3) {
         const unsigned long long v = part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] +
                                      part[3][threadIdx.x];
         atomicAdd(F.stat + threadIdx.x, v);
+    } else if (threadIdx.x == 3) {
+        const unsigned long long v = max(max(part[0][3], part[1][3]), max(part[2][3], part[3][3]));
+        atomicMax(F.stat + 3, v);
     }
 }
 

@@ -504,7 +504,7 @@ dic_status dic_server_step(dic_server *s, int32_t steps)
                 S.iterations = static_cast<int64_t>(stat[4 * i + 2]);
                 S.frames = 1;
                 S.threads_per_subset = r->ref->tps;
-                S.waves = s->step - r->F.k_base;
+                S.waves = static_cast<int32_t>(stat[4 * i + 3]);
                 release(s, r);
                 r->state = 2;
                 ++s->completed;

@@ -17,8 +17,9 @@ CONFIGS = {
     "c": ("c3", 192, dict(shape=12)),                       # quadratic, N21, 64 threads
     "d": ("c1", 192, dict(N=15, step=3, seed_blobs=1011)),  # N15: shares the launch of "a"
     "e": ("c2", 256, dict(seed_blobs=2011)),                # FP32 reductions: its own launch
+    "f": ("c1", 224, dict(seed_blobs=1021)),                # FP16 coefficients, in the launch of "a"
 }
-PARAMS_OVER = {"e": dict(reduce_fp64=False)}
+PARAMS_OVER = {"e": dict(reduce_fp64=False), "f": dict(coef_fp16=True)}
 
 
 def _setup():
@@ -51,6 +52,7 @@ def _alone(refs, frames):
             r = eng.correlate(f, w.seeds)
             torch.cuda.synchronize()
             out[(key, i)] = {k: v.cpu().numpy() for k, v in r.items()}
+            out[(key, i)]["waves"] = eng.stats()["waves"]
         eng.close()
     return out
 
@@ -81,7 +83,7 @@ def test_mixed_requests_equal_alone():
     submit("d", 0)
     submit("a", 1)
     srv.step(2)
-    for key, i in (("e", 0), ("b", 1), ("c", 1), ("d", 1), ("e", 1)):
+    for key, i in (("e", 0), ("b", 1), ("c", 1), ("d", 1), ("f", 0), ("e", 1), ("f", 1)):
         submit(key, i)
     results = {}
     for _ in range(2000):
@@ -104,6 +106,7 @@ def test_mixed_requests_equal_alone():
     for tag, (res, st) in results.items():
         _equal(res, alone[tag], tag)
         assert st["converged"] == int((res["status"] == 0).sum()), tag
+        assert st["waves"] == alone[tag]["waves"] == int(res["wave"].max()) + 1, tag
     # one request against the FP64 oracle as well
     w, pair, _ = refs["a"]
     compare(results[("a", 0)][0], oracle_run(pair, w))
