@@ -966,8 +966,13 @@ __device__ __forceinline__ void compose_quadratic(double (&p)[12], const double 
 // ---------------------------------------------------------------------------
 // One frontier wave: every subset of wave k of every frame.
 // ---------------------------------------------------------------------------
+// Register blocks of at most 4 rows fit three wavefronts per SIMD without spilling;
+// ask the compiler for that occupancy there (the latency-bound single-frame form
+// runs them).
+template <int NP, int P> constexpr int wave_occupancy_hint() { return (NP == 6 && P <= 4) ? 3 : 1; }
+
 template <int NP, int T, int P, bool F64>
-__global__ __launch_bounds__(T) void k_wave(const FrameTable frames, int step)
+__global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(const FrameTable frames, int step)
 {
     using Acc = typename std::conditional<F64, double, float>::type;
     constexpr int NS = 3 + NP;
@@ -1231,6 +1236,7 @@ __global__ __launch_bounds__(T) void k_wave(const FrameTable frames, int step)
                     const float dyl = static_cast<float>(N - 1 - h);
                     const float Xc = fmaf(A1, dxf, A0), Yc = fmaf(B1, dxf, B0);
                     const float *tb = tile - ts - 1;
+                    const float tsf = static_cast<float>(ts);
                     // rows per thread of this subset (a launch may mix subset sizes, P is
                     // the largest); uniform across the workgroup
                     const int JM = __builtin_amdgcn_readfirstlane((N + L.R - 1) / L.R);
@@ -1250,7 +1256,9 @@ __global__ __launch_bounds__(T) void k_wave(const FrameTable frames, int step)
                             float wx0, wx1, wx2, wx3, wy0, wy1, wy2, wy3;
                             bspline_w(X - fx0, wx0, wx1, wx2, wx3);
                             bspline_w(Y - fy0, wy0, wy1, wy2, wy3);
-                            const int off = static_cast<int>(fy0) * ts + static_cast<int>(fx0);
+                            // tap offset in the window: exact in FP32 (|values| < 2^24), which
+                            // avoids a quarter-rate integer multiply per pixel
+                            const int off = static_cast<int>(fmaf(fy0, tsf, fx0));
                             const float g = interp16(tb + off, ts, wx0, wx1, wx2, wx3, wy0, wy1, wy2, wy3);
                             accumulate<NP>(s, on ? g - fm32 : 0.0f, fb[j], gx[j], gy[j], dxf, dy);
                         }
