@@ -88,7 +88,9 @@ typedef struct {
     int32_t coef_fp16;          /* 1: deformed-image spline coefficients stored as FP16 */
     int32_t reduce_fp64;        /* 1: cross-lane sums and the normal-equation solve in FP64; 0: FP32 */
     int32_t nan_unconverged;    /* 1: write NaN into p of every node that is not CONVERGED */
-    int32_t threads_per_subset; /* 0 = automatic; else 64, 128 or 256 */
+    int32_t threads_per_subset; /* 0 = automatic; else 64, 128 or 256 threads (one workgroup) per subset,
+                                   or 16 / 32: four / two subsets share one 64-lane wavefront
+                                   (affine shape, N <= 16) */
     int32_t tile_side;          /* side of the LDS window of deformed coefficients, in samples:
                                    0 = automatic (N + 17 rounded up to a multiple of 16), else
                                    N + 5 .. 96; a warped subset that does not fit reads global memory */

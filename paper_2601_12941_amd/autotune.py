@@ -29,7 +29,9 @@ def candidates(N: int, shape: int = 6):
     tiles = sorted({t for t in (default_tile(N) - 16, default_tile(N), default_tile(N) + 16)
                     if N + 5 <= t <= 96})
     out = []
-    for tps in (64, 128, 256):
+    for tps in (16, 32, 64, 128, 256):
+        if tps < 64 and (shape != 6 or N > 16):
+            continue   # packed subsets: affine, N <= 16
         if tps < N:
             continue
         for ts in tiles:

@@ -107,6 +107,8 @@ dic_status dic_set_reference(dic_ctx *c, const dic_image *ref, const uint8_t *ro
         FAIL(DIC_E_INVAL, "threads_per_subset %d unsupported for subset %d", tps, p.subset_size);
     if (p.tile_side != 0 && (p.tile_side < p.subset_size + 5 || p.tile_side > 96))
         FAIL(DIC_E_INVAL, "tile_side %d (0, or %d..96)", p.tile_side, p.subset_size + 5);
+    if (tps < 64 && p.shape != DIC_SHAPE_AFFINE)
+        FAIL(DIC_E_UNSUPPORTED, "packed subsets (%d threads per subset) are built for the affine shape", tps);
     if (p.shape == DIC_SHAPE_QUADRATIC && tps == 64 && p.subset_size > 21)
         FAIL(DIC_E_UNSUPPORTED, "quadratic shape with 64 threads is built for subsets up to 21");
 

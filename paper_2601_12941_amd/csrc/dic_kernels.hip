@@ -1438,6 +1438,402 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
 }
 
 // ---------------------------------------------------------------------------
+// Packed subsets: for small subsets (N <= 16, affine) one wavefront carries
+// 64 / LS subsets, LS lanes each (column-per-thread inside its lane group).
+// The per-iteration scalar work (reductions, checks, solve, composition) is
+// then shared by the subsets of the wavefront instead of repeated per subset.
+// The group's sums use the first steps of the wavefront reduction (the lanes
+// of one 16- or 32-lane segment), in the same order on the reference side.
+// ---------------------------------------------------------------------------
+template <int LS, typename V> __device__ __forceinline__ V seg_allreduce(V v)
+{
+    v += dpp_read<0xB1>(v);
+    v += dpp_read<0x4E>(v);
+    v += dpp_read<0x141>(v);
+    v += dpp_read<0x140>(v);
+    if constexpr (LS >= 32) v = pair_sum16(v);
+    return v;
+}
+
+template <int LS, int P>
+__global__ __launch_bounds__(64) void k_ref_nodes_packed(RefView R, double *cache, int8_t *flag)
+{
+    constexpr int NP = 6, NH = NP * (NP + 1) / 2, NB = NP + NH, G = 64 / LS;
+    const int t = threadIdx.x, g = t / LS, tl = t - g * LS;
+    const int N = R.N, h = (N - 1) / 2, n = N * N;
+    const Columns L(tl, LS, N);
+    const float dxf = static_cast<float>(L.c - h);
+    const float dy0 = static_cast<float>(L.r0 - h), dyR = static_cast<float>(L.R);
+    const int64_t nn = R.nodes;
+    const int64_t rstep = static_cast<int64_t>(L.R) * R.ppitch;
+    for (int64_t base = static_cast<int64_t>(blockIdx.x) * G; base < nn; base += static_cast<int64_t>(gridDim.x) * G) {
+        const int64_t node = base + g;
+        const bool valid = node < nn && flag[node] >= 0;
+        const int xc = h + static_cast<int>((valid ? node : 0) % R.nx) * R.step;
+        const int yc = h + static_cast<int>((valid ? node : 0) / R.nx) * R.step;
+        const int64_t o0 = static_cast<int64_t>(yc - h + L.r0) * R.ppitch + xc - h + L.c;
+        double sf = 0.0;
+#pragma unroll
+        for (int j = 0; j < P; ++j)
+            if (valid && j < L.jmax) sf += static_cast<double>(R.pf[o0 + j * rstep]);
+        sf = seg_allreduce<LS>(sf);
+        const double fm = sf / n;
+        const float fm32 = static_cast<float>(fm);
+        float s[3 + NP];
+#pragma unroll
+        for (int i = 0; i < 3 + NP; ++i) s[i] = 0.0f;
+        double vb[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) vb[i] = 0.0;
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            if (valid && j < L.jmax) {
+                const int64_t o = o0 + j * rstep;
+                const float fb = R.pf[o] - fm32;
+                const float gx = R.pfx[o], gy = R.pfy[o];
+                const float dyf = fmaf(static_cast<float>(j), dyR, dy0);
+                accumulate<NP>(s, fb, fb, gx, gy, dxf, dyf);
+                double J[NP];
+                steepest<NP>(J, gx, gy, dxf, dyf);
+                int q = NP;
+#pragma unroll
+                for (int a = 0; a < NP; ++a) {
+                    vb[a] += J[a];
+#pragma unroll
+                    for (int b = a; b < NP; ++b) {
+                        vb[q] = fma(J[a], J[b], vb[q]);
+                        ++q;
+                    }
+                }
+            }
+        }
+        double va[3 + NP];
+#pragma unroll
+        for (int i = 0; i < 3 + NP; ++i) va[i] = seg_allreduce<LS>(static_cast<double>(s[i]));
+#pragma unroll
+        for (int i = 0; i < NB; ++i) vb[i] = seg_allreduce<LS>(vb[i]);
+        if (valid && tl == 0) {
+            cache[node] = fm;
+            cache[1 * nn + node] = va[1];
+            cache[2 * nn + node] = va[0];
+#pragma unroll
+            for (int a = 0; a < NP; ++a) cache[(3 + NP + a) * nn + node] = va[3 + a];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) cache[static_cast<int64_t>(slot_b<NP>(i)) * nn + node] = vb[i];
+        }
+    }
+}
+
+template <int LS, int P, bool F64>
+__global__ __launch_bounds__(64) void k_wave_packed(const FrameTable frames, int step)
+{
+    using Acc = typename std::conditional<F64, double, float>::type;
+    constexpr int NP = 6, NS = 3 + NP, NH = NP * (NP + 1) / 2, NC = 3 + 2 * NP + NH, G = 64 / LS;
+    extern __shared__ float tiles[];   // G windows of ts * ts deformed coefficients
+    __shared__ double cache[G][NC];
+    __shared__ int prefix[kMaxFrames + 1];
+    __shared__ int owned[kMaxFrames + 1];
+    __shared__ int cnt[kMaxFrames];
+    const int nframes = frames.n;
+    // frame affinity as in k_wave; the work items are slots of G subsets of one frame
+    const int XG = (nframes % 8 == 0 && gridDim.x % 8 == 0) ? 8 : 1;
+    const int grp = static_cast<int>(blockIdx.x) % XG;
+    const int gb = static_cast<int>(blockIdx.x) / XG, gstride = static_cast<int>(gridDim.x) / XG;
+    const int t = threadIdx.x, g = t / LS, tl = t - g * LS;
+    if (t == 0) {
+        int acc = 0, m = 0;
+        for (int f = grp; f < nframes; f += XG, ++m) {
+            owned[m] = f;
+            prefix[m] = acc;
+            const int kf = step - frames.f[f].k_base;
+            const int c = (kf >= 0 && kf <= frames.f[f].kmax) ? frames.f[f].counts[kf] : 0;
+            cnt[m] = c;
+            acc += (c + G - 1) / G;
+        }
+        owned[kMaxFrames] = m;
+        prefix[m] = acc;
+    }
+    __syncthreads();
+    const int nown = __builtin_amdgcn_readfirstlane(owned[kMaxFrames]);
+    const int total = __builtin_amdgcn_readfirstlane(prefix[nown]);
+    if (gb >= total) return;
+
+    for (int si = gb; si < total; si += gstride) {
+        int m = 0;
+        while (m + 1 < nown && prefix[m + 1] <= si) ++m;
+        m = __builtin_amdgcn_readfirstlane(m);
+        const int f = __builtin_amdgcn_readfirstlane(owned[m]);
+        const FrameState &F = frames.f[f];
+        const RefView R = *F.ref;
+        const int k = step - F.k_base;
+        const int ts = R.ts, half = R.half;
+        const int N = R.N, h = (N - 1) / 2, n = N * N;
+        const double inv_n = 1.0 / n;
+        const int64_t nn = R.nodes;
+        const Columns L(tl, LS, N);
+        const float dxf = static_cast<float>(L.c - h);
+        const float dy0 = static_cast<float>(L.r0 - h), dyR = static_cast<float>(L.R);
+        const int li = (si - prefix[m]) * G + g;   // this group's position in the frame's list
+        const bool act = li < cnt[m];
+        const int32_t *lin = (k & 1) ? F.list1 : F.list0;
+        int32_t *lout = (k & 1) ? F.list0 : F.list1;
+        const int node = act ? lin[li] : 0;
+        const int ix = node % R.nx, iy = node / R.nx;
+        const int xc = h + ix * R.step, yc = h + iy * R.step;
+        const int8_t rf = act ? R.flag[node] : static_cast<int8_t>(-1);
+        const uint64_t key = (act && k > 0) ? F.pkey[node] : 0;
+        float qa[4][NP];
+        if (act && k > 0) {
+            const int64_t nb[4] = {static_cast<int64_t>(iy) * R.nx + max(ix - 1, 0),
+                                   static_cast<int64_t>(iy) * R.nx + min(ix + 1, R.nx - 1),
+                                   static_cast<int64_t>(max(iy - 1, 0)) * R.nx + ix,
+                                   static_cast<int64_t>(min(iy + 1, R.ny - 1)) * R.nx + ix};
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+#pragma unroll
+                for (int j = 0; j < NP; ++j) qa[d][j] = F.p[j * nn + nb[d]];
+        }
+        __syncthreads();   // the previous slot is done with the LDS cache and windows
+        if (act)
+            for (int q = tl; q < NC; q += LS) cache[g][q] = R.cache[static_cast<int64_t>(q) * nn + node];
+        float fb[P], gx[P], gy[P];
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            fb[j] = gx[j] = gy[j] = 0.0f;
+            if (act && j < L.jmax) {
+                const int64_t o = static_cast<int64_t>(yc - h + L.r0 + L.R * j) * R.ppitch + xc - h + L.c;
+                fb[j] = R.pf[o];
+                gx[j] = R.pfx[o];
+                gy[j] = R.pfy[o];
+            }
+        }
+        double p[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) p[j] = 0.0;
+        if (act && k == 0) {
+            p[0] = F.seed_p[2 * li];
+            p[1] = F.seed_p[2 * li + 1];
+        } else if (act) {
+            const uint32_t dir = static_cast<uint32_t>(key & 3u);
+            const int px = ix + (dir == 3 ? -1 : (dir == 2 ? 1 : 0));
+            const int py = iy + (dir == 1 ? -1 : (dir == 0 ? 1 : 0));
+            const int sel = dir == 3 ? 0 : (dir == 2 ? 1 : (dir == 1 ? 2 : 3));
+            double q[NP];
+#pragma unroll
+            for (int j = 0; j < NP; ++j)
+                q[j] = static_cast<double>(sel == 0 ? qa[0][j] : (sel == 1 ? qa[1][j] : (sel == 2 ? qa[2][j] : qa[3][j])));
+#pragma unroll
+            for (int j = 0; j < NP; ++j) p[j] = q[j];
+            if (!R.guess_copy) {
+                const double ex = static_cast<double>((ix - px) * R.step);
+                const double ey = static_cast<double>((iy - py) * R.step);
+                p[0] = q[0] + q[2] * ex + q[3] * ey;
+                p[1] = q[1] + q[4] * ex + q[5] * ey;
+            }
+        }
+        __syncthreads();   // caches visible
+        int status = act ? (rf != 0 ? static_cast<int>(rf) : kMaxIter) : kMaxIter;
+        int iters = 0;
+        float zncc_out = 0.0f;
+        bool live = act && rf == 0;
+        const double *cg = cache[g];
+        float *tile = tiles + g * ts * ts;
+        const float fm32 = static_cast<float>(cg[0]);
+#pragma unroll
+        for (int j = 0; j < P; ++j)
+            if (live && j < L.jmax) fb[j] -= fm32;
+        const double hd = static_cast<double>(h);
+        int tox = INT_MIN / 2, toy = INT_MIN / 2;
+        for (int it = 1; it <= R.max_iter; ++it) {
+            if (__ballot(live) == 0) break;
+            bool fits = false;
+            int ox = 0, oy = 0;
+            if (live) {
+                iters = it;
+                const double ux = (1.0 + p[2]) * hd, uy = p[3] * hd;
+                const double vx = p[4] * hd, vy = (1.0 + p[5]) * hd;
+                const double cx = xc + p[0], cy = yc + p[1];
+                const double rx = fabs(ux) + fabs(uy), ry = fabs(vx) + fabs(vy);
+                const double xmin = cx - rx, xmax = cx + rx, ymin = cy - ry, ymax = cy + ry;
+                if (isnan(xmin + xmax + ymin + ymax)) {
+                    status = kNan;
+                    live = false;
+                } else if (!(xmin >= 0.0 && xmax <= R.W - 1.0 && ymin >= 0.0 && ymax <= R.H - 1.0)) {
+                    status = kOutOfBounds;
+                    zncc_out = 0.0f;
+                    live = false;
+                } else {
+                    const int tx0 = static_cast<int>(floor(xmin - 1e-3)) - 1, tx1 = static_cast<int>(floor(xmax + 1e-3)) + 2;
+                    const int ty0 = static_cast<int>(floor(ymin - 1e-3)) - 1, ty1 = static_cast<int>(floor(ymax + 1e-3)) + 2;
+                    fits = (tx1 - tx0 < ts) && (ty1 - ty0 < ts) && (R.W + 2 * kPad >= ts) && (R.H + 2 * kPad >= ts);
+                    if (fits && !(tx0 >= tox && tx1 < tox + ts && ty0 >= toy && ty1 < toy + ts)) {
+                        int nx0 = tx0 - (ts - (tx1 - tx0 + 1)) / 2;
+                        int ny0 = ty0 - (ts - (ty1 - ty0 + 1)) / 2;
+                        nx0 = max(-kPad, min(nx0, R.W + kPad - ts));
+                        ny0 = max(-kPad, min(ny0, R.H + kPad - ts));
+                        tox = nx0;
+                        toy = ny0;
+                        // this group's lanes restage its own window
+                        for (int e = tl; e < ts * ts; e += LS) {
+                            const int r = e / ts, c = e - r * ts;
+                            const int64_t go = static_cast<int64_t>(toy + r) * F.dpitch + (tox + c);
+                            tile[e] = half ? to_f32(static_cast<const __half *>(F.dcoef)[go])
+                                           : static_cast<const float *>(F.dcoef)[go];
+                        }
+                    }
+                    ox = fits ? tox : static_cast<int>(floor(xc + p[0])) - h - 4;
+                    oy = fits ? toy : static_cast<int>(floor(yc + p[1])) - h - 4;
+                }
+            }
+            __syncthreads();   // windows written
+            float s[NS];
+#pragma unroll
+            for (int i = 0; i < NS; ++i) s[i] = 0.0f;
+            if (live) {
+                const float A0 = static_cast<float>(static_cast<double>(xc - ox) + p[0]);
+                const float A1 = static_cast<float>(1.0 + p[2]);
+                const float A2 = static_cast<float>(p[3]);
+                const float B0 = static_cast<float>(static_cast<double>(yc - oy) + p[1]);
+                const float B1 = static_cast<float>(p[4]);
+                const float B2 = static_cast<float>(1.0 + p[5]);
+                const float X0 = fmaf(A2, dy0, fmaf(A1, dxf, A0)), XR = A2 * dyR;
+                const float Y0 = fmaf(B2, dy0, fmaf(B1, dxf, B0)), YR = B2 * dyR;
+#pragma unroll
+                for (int j = 0; j < P; ++j) {
+                    if (j < L.jmax) {
+                        const float dy = fmaf(static_cast<float>(j), dyR, dy0);
+                        const float X = fmaf(static_cast<float>(j), XR, X0);
+                        const float Y = fmaf(static_cast<float>(j), YR, Y0);
+                        const float fx0 = floorf(X), fy0 = floorf(Y);
+                        float wx0, wx1, wx2, wx3, wy0, wy1, wy2, wy3;
+                        bspline_w(X - fx0, wx0, wx1, wx2, wx3);
+                        bspline_w(Y - fy0, wy0, wy1, wy2, wy3);
+                        const int ixl = static_cast<int>(fx0) - 1, iyl = static_cast<int>(fy0) - 1;
+                        float gv;
+                        if (fits) {
+                            gv = interp16(tile + iyl * ts + ixl, ts, wx0, wx1, wx2, wx3, wy0, wy1, wy2, wy3);
+                        } else {
+                            const int64_t go = static_cast<int64_t>(oy + iyl) * F.dpitch + (ox + ixl);
+                            gv = half ? interp16(static_cast<const __half *>(F.dcoef) + go, F.dpitch, wx0, wx1, wx2,
+                                                 wx3, wy0, wy1, wy2, wy3)
+                                      : interp16(static_cast<const float *>(F.dcoef) + go, F.dpitch, wx0, wx1, wx2,
+                                                 wx3, wy0, wy1, wy2, wy3);
+                        }
+                        accumulate<NP>(s, gv - fm32, fb[j], gx[j], gy[j], dxf, dy);
+                    }
+                }
+            }
+            // segmented sums over each group's lanes (every lane takes part)
+            Acc v[NS];
+#pragma unroll
+            for (int i = 0; i < NS; ++i) v[i] = seg_allreduce<LS>(static_cast<Acc>(s[i]));
+            if (live) {
+                do {
+                    const Acc S0 = v[0], S1 = v[1];
+                    const Acc gm = S0 * static_cast<Acc>(inv_n);
+                    const Acc dg2 = S1 - S0 * gm;
+                    if (isnan(static_cast<double>(dg2))) { status = kNan; live = false; break; }
+                    const double lev = fmax(1.0, fabs(cg[0] + static_cast<double>(gm)));
+                    if (static_cast<double>(dg2) <= n * (kFlatRel * lev) * (kFlatRel * lev)) {
+                        status = kFlatDef;
+                        zncc_out = 0.0f;
+                        live = false;
+                        break;
+                    }
+                    const Acc sfg = v[2] - gm * static_cast<Acc>(cg[2]);
+                    const float ratio_f = sqrtf(static_cast<float>(cg[1]) / static_cast<float>(dg2));
+                    const float zn = static_cast<float>(sfg) / (static_cast<float>(dg2) * ratio_f);
+                    const Acc ratio = static_cast<Acc>(ratio_f);
+                    Acc b[NP];
+#pragma unroll
+                    for (int a = 0; a < NP; ++a)
+                        b[a] = static_cast<Acc>(cg[3 + NP + a]) - ratio * (v[3 + a] - gm * static_cast<Acc>(cg[3 + a]));
+                    {
+#pragma clang fp contract(fast)
+                        double dp[NP];
+                        {
+                            int q = 0;
+                            Acc acc[NP];
+#pragma unroll
+                            for (int a = 0; a < NP; ++a) acc[a] = 0;
+#pragma unroll
+                            for (int a = 0; a < NP; ++a)
+#pragma unroll
+                                for (int c = a; c < NP; ++c) {
+                                    const Acc hv = static_cast<Acc>(cg[3 + 2 * NP + q]);
+                                    ++q;
+                                    acc[a] += hv * b[c];
+                                    if (c != a) acc[c] += hv * b[a];
+                                }
+#pragma unroll
+                            for (int a = 0; a < NP; ++a) dp[a] = -static_cast<double>(acc[a]);
+                        }
+                        zncc_out = zn;
+                        compose_affine(p, dp);
+                        double s1 = 0.0;
+#pragma unroll
+                        for (int a = 2; a < 6; ++a) s1 += dp[a] * dp[a];
+                        const double nrm = dp[0] * dp[0] + dp[1] * dp[1] + hd * hd * s1;
+                        bool bad = isnan(zn) || isnan(nrm);
+#pragma unroll
+                        for (int a = 0; a < NP; ++a) bad = bad || isnan(p[a]);
+                        if (bad) { status = kNan; live = false; break; }
+                        if (nrm < R.tol2) {
+                            status = zncc_out >= R.zncc_min ? kConverged : kLowZncc;
+                            live = false;
+                        }
+                    }
+                } while (false);
+            }
+        }
+        if (act && tl == 0) {
+#pragma unroll
+            for (int j = 0; j < NP; ++j) F.p[j * nn + node] = static_cast<float>(p[j]);
+            F.zncc[node] = zncc_out;
+            F.iters[node] = static_cast<int16_t>(iters);
+            F.status[node] = static_cast<int8_t>(status);
+        }
+        // propagation: lanes 0..3 of each group visit the group's four neighbours
+        int64_t mnb = -1;
+        bool inserted = false;
+        if (act && status == kConverged && tl < 4) {
+            const int cx = ix + (tl == 0 ? 1 : (tl == 1 ? -1 : 0));
+            const int cy = iy + (tl == 2 ? 1 : (tl == 3 ? -1 : 0));
+            if (cx >= 0 && cy >= 0 && cx < R.nx && cy < R.ny) {
+                mnb = static_cast<int64_t>(cy) * R.nx + cx;
+                if (R.flag[mnb] >= 0) {
+                    const int old = atomicCAS(F.wave + mnb, -1, k + 1);
+                    inserted = old == -1;
+                    if (old == -1 || old == k + 1)
+                        atomicMax(reinterpret_cast<unsigned long long *>(F.pkey + mnb),
+                                  static_cast<unsigned long long>(
+                                      (static_cast<uint64_t>(ordered_bits(zncc_out)) << 2) | (3u - tl)));
+                }
+            }
+        }
+        const uint64_t bal = __ballot(inserted);
+        if (bal != 0) {
+            int basei = 0;
+            if (t == 0) basei = atomicAdd(F.counts + k + 1, __popcll(bal));
+            basei = __shfl(basei, 0);
+            if (inserted) lout[basei + __popcll(bal & ((1ull << t) - 1))] = static_cast<int32_t>(mnb);
+        }
+    }
+}
+
+template <int LS, int P>
+static void wave_packed_inst(const FrameTable &F, int step, bool f64, int max_ts, int grid, hipStream_t s)
+{
+    const size_t lds = static_cast<size_t>(64 / LS) * max_ts * max_ts * sizeof(float);
+    if (f64)
+        k_wave_packed<LS, P, true><<<grid, 64, lds, s>>>(F, step);
+    else
+        k_wave_packed<LS, P, false><<<grid, 64, lds, s>>>(F, step);
+}
+
+#define DIC_PACKED_CASES(X) X(16, 8) X(16, 12) X(16, 16) X(32, 2) X(32, 4) X(32, 8)
+
+// ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
 template <int NP, int T, int P>
@@ -1482,6 +1878,17 @@ bool launch_wave(const FrameTable &F, int step, int np, int N, int tps, bool f64
                  hipStream_t s)
 {
     const int P = pixels_per_thread(N, tps);
+    if (tps < 64) {
+        if (np != 6) return false;
+#define X(LS_, P_)                                                                                                    \
+    if (tps == LS_ && P == P_) {                                                                                      \
+        wave_packed_inst<LS_, P_>(F, step, f64, max_ts, grid, s);                                                     \
+        return true;                                                                                                   \
+    }
+        DIC_PACKED_CASES(X)
+#undef X
+        return false;
+    }
 #define X(NP_, T_, P_)                                                                                                \
     if (np == NP_ && tps == T_ && P == P_) {                                                                          \
         wave_inst<NP_, T_, P_>(F, step, f64, max_ts, grid, s);                                      \
@@ -1496,6 +1903,19 @@ bool launch_wave(const FrameTable &F, int step, int np, int N, int tps, bool f64
 void launch_ref_nodes(const RefView &R, int np, int tps, double *cache, int8_t *flag, hipStream_t s)
 {
     const int P = pixels_per_thread(R.N, tps);
+    if (tps < 64) {
+        const int64_t nblk = (R.nodes + 64 / tps - 1) / (64 / tps);
+        const unsigned grid = static_cast<unsigned>(nblk < 8192 ? (nblk < 1 ? 1 : nblk) : 8192);
+#define X(LS_, P_)                                                                                                    \
+    if (np == 6 && tps == LS_ && P == P_) {                                                                           \
+        k_ref_nodes_packed<LS_, P_><<<grid, 64, 0, s>>>(R, cache, flag);                                              \
+        k_ref_factor<6><<<static_cast<unsigned>((R.nodes + 255) / 256), 256, 0, s>>>(R, cache, flag);               \
+        return;                                                                                                        \
+    }
+        DIC_PACKED_CASES(X)
+#undef X
+        return;
+    }
 #define X(NP_, T_, P_)                                                                                                \
     if (np == NP_ && tps == T_ && P == P_) {                                                                          \
         ref_nodes_inst<NP_, T_, P_>(R, cache, flag, s);                                                               \
@@ -1508,6 +1928,11 @@ void launch_ref_nodes(const RefView &R, int np, int tps, double *cache, int8_t *
 
 bool supported_tps(int N, int tps)
 {
+    if (tps == 16 || tps == 32) {
+        // packed subsets (affine only, checked by the caller)
+        const int P = pixels_per_thread(N, tps);
+        return tps == 16 ? (P == 8 || P == 12 || P == 16) : (P == 2 || P == 4 || P == 8);
+    }
     if (tps != 64 && tps != 128 && tps != 256) return false;
     const int P = pixels_per_thread(N, tps);
     return P > 0 && !(tps == 64 && P < 4);
@@ -1518,7 +1943,7 @@ int wave_grid_hint(int np, int tps, int device)
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     // enough workgroups to keep every SIMD busy with a few subsets each
-    const int per_cu = tps == 64 ? 16 : (tps == 128 ? 8 : 4);
+    const int per_cu = tps <= 64 ? 16 : (tps == 128 ? 8 : 4);
     (void)np;
     return cus * per_cu;
 }

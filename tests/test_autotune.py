@@ -15,9 +15,11 @@ def test_candidates_respect_the_window_and_wavefront_limits():
         c = autotune.candidates(N)
         assert c, N
         for tps, ts in c:
-            assert tps in (64, 128, 256) and tps >= N
+            assert tps in (16, 32, 64, 128, 256) and tps >= N
+            assert tps >= 64 or N <= 16     # packed subsets only for N <= 16
             assert N + 5 <= ts <= 96
-    assert {t for t, _ in autotune.candidates(15)} == {64, 128, 256}
+    assert {t for t, _ in autotune.candidates(15)} == {16, 32, 64, 128, 256}
+    assert {t for t, _ in autotune.candidates(15, shape=12)} == {64, 128, 256}
     assert sorted({s for _, s in autotune.candidates(31)}) == [48, 64]
     assert sorted({s for _, s in autotune.candidates(63)}) == [80, 96]
 
