@@ -451,6 +451,7 @@ def serve(args):
                 if not done:
                     continue
                 i, out, rid = inflight.pop(t)
+                srv.forget(t)
                 inuse[rid] -= 1
                 if status != dic.DIC_OK:
                     raise RuntimeError("request %d failed with status %d" % (i, status))

@@ -239,6 +239,11 @@ dic_status dic_server_step(dic_server *s, int32_t steps);
  * (may be NULL) receives the request's counters. */
 dic_status dic_server_poll(dic_server *s, int64_t ticket, int32_t *done, int32_t *status, dic_stats *st);
 
+/* Drop the record of a finished request (its ticket becomes unknown); a
+ * long-running server calls it once a result has been consumed.  DIC_E_STATE
+ * if the request is not done yet. */
+dic_status dic_server_forget(dic_server *s, int64_t ticket);
+
 dic_status dic_server_get_stats(const dic_server *s, dic_server_stats *out);
 dic_status dic_server_destroy(dic_server *s);
 const char *dic_server_last_error(const dic_server *s);

@@ -527,6 +527,18 @@ dic_status dic_server_poll(dic_server *s, int64_t ticket, int32_t *done, int32_t
     return DIC_OK;
 }
 
+dic_status dic_server_forget(dic_server *s, int64_t ticket)
+{
+    if (!s) return DIC_E_INVAL;
+    s->err.clear();
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) SFAIL(DIC_E_INVAL, "unknown ticket %lld", static_cast<long long>(ticket));
+    if (it->second->state != 2) SFAIL(DIC_E_STATE, "ticket %lld is not done", static_cast<long long>(ticket));
+    delete it->second;
+    s->all.erase(it);
+    return DIC_OK;
+}
+
 dic_status dic_server_get_stats(const dic_server *s, dic_server_stats *out)
 {
     if (!s || !out) return DIC_E_INVAL;

@@ -31,7 +31,7 @@ NODE = dict(CONVERGED=0, NOT_REACHED=1, NOT_IN_ROI=2, MAX_ITER=3, LOW_ZNCC=4, OU
 EXPORTS = ["dic_create", "dic_set_reference", "dic_grid_shape", "dic_correlate", "dic_correlate_batch",
            "dic_get_stats", "dic_destroy", "dic_last_error",
            "dic_server_create", "dic_server_add_reference", "dic_server_remove_reference", "dic_server_submit",
-           "dic_server_step", "dic_server_poll", "dic_server_get_stats", "dic_server_destroy",
+           "dic_server_step", "dic_server_poll", "dic_server_forget", "dic_server_get_stats", "dic_server_destroy",
            "dic_server_last_error"]
 
 
@@ -108,6 +108,7 @@ def load_library(path: str = LIB_PATH):
                                     P(C.c_int64)]
     L.dic_server_step.argtypes = [C.c_void_p, C.c_int32]
     L.dic_server_poll.argtypes = [C.c_void_p, C.c_int64, P(C.c_int32), P(C.c_int32), P(DicStats)]
+    L.dic_server_forget.argtypes = [C.c_void_p, C.c_int64]
     L.dic_server_get_stats.argtypes = [C.c_void_p, P(DicServerStats)]
     L.dic_server_destroy.argtypes = [C.c_void_p]
     L.dic_server_last_error.argtypes = [C.c_void_p]
@@ -223,6 +224,10 @@ def dic_server_poll(srv, ticket: int):
     done, status, st = C.c_int32(), C.c_int32(), DicStats()
     _scheck(srv, load_library().dic_server_poll(srv, int(ticket), C.byref(done), C.byref(status), C.byref(st)))
     return bool(done.value), status.value, {k: getattr(st, k) for k, _ in DicStats._fields_}
+
+
+def dic_server_forget(srv, ticket: int):
+    _scheck(srv, load_library().dic_server_forget(srv, int(ticket)))
 
 
 def dic_server_get_stats(srv) -> dict:
@@ -437,6 +442,10 @@ class Server:
         if done:
             self._live.pop(ticket, None)
         return done, status, st
+
+    def forget(self, ticket: int):
+        """Drop a finished request's record in the library (the ticket becomes unknown)."""
+        dic_server_forget(self.srv, ticket)
 
     def stats(self) -> dict:
         return dic_server_get_stats(self.srv)

@@ -101,6 +101,7 @@ def test_calls_without_a_device_fail_cleanly():
     assert L.dic_server_step(None, 1) == dic.DIC_E_INVAL
     assert L.dic_server_poll(None, 1, None, None, None) == dic.DIC_E_INVAL
     assert L.dic_server_get_stats(None, None) == dic.DIC_E_INVAL
+    assert L.dic_server_forget(None, 1) == dic.DIC_E_INVAL
     assert L.dic_server_destroy(None) == dic.DIC_E_INVAL
     assert L.dic_server_last_error(None) == b"null server"
 

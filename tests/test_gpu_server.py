@@ -199,6 +199,10 @@ def test_request_errors():
         if done:
             break
     assert done and status == dic.DIC_OK
+    # a finished request's record can be dropped; an unknown ticket is an error
+    srv.forget(t)
+    with pytest.raises(dic.DicError):
+        srv.poll(t)
     # a reference with an empty region has no node a seed can snap to
     r0 = srv.add_reference(ref, torch.zeros_like(roi), **w.params())
     t, _ = srv.submit(r0, de, w.seeds)
