@@ -434,7 +434,9 @@ def serve(args):
         while nxt < len(trace) and trace[nxt].arrival <= now:
             pending.append(nxt)
             nxt += 1
-        while pending:
+        # hand requests to the server while its own queue is short, so that queued
+        # requests do not pin references that idle ones could make room for
+        while pending and srv.stats()["waiting"] < 2:
             q = trace[pending[0]]
             rid = ensure(q)
             if rid is None:
@@ -446,6 +448,13 @@ def serve(args):
             pending.popleft()
         if inflight:
             srv.step(args.chunk)
+            ss = srv.stats()
+            if ss["waiting"] > 0 and ss["active"] < args.max_active:
+                # admission is held by the budget: release the least recently used idle reference
+                idle = [k for k, v in resident.items() if inuse[v] == 0]
+                if idle:
+                    srv.remove_reference(resident.pop(idle[0]))
+                    reg["evictions"] += 1
             for t in list(inflight):
                 done, status, st = srv.poll(t)
                 if not done:

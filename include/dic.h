@@ -235,7 +235,9 @@ dic_status dic_server_submit(dic_server *s, int32_t ref_id, const dic_image *def
 dic_status dic_server_step(dic_server *s, int32_t steps);
 
 /* *done = 1 once the request's results are final; *status is then DIC_OK or
- * the request's error (DIC_E_NOSEED, DIC_E_NOMEM if it can never fit).  st
+ * the request's error (DIC_E_NOSEED; DIC_E_NOMEM if its scratch does not fit
+ * the budget even beside its own reference alone).  A request that does not
+ * fit now waits at the head of the queue.  st
  * (may be NULL) receives the request's counters. */
 dic_status dic_server_poll(dic_server *s, int64_t ticket, int32_t *done, int32_t *status, dic_stats *st);
 

@@ -46,6 +46,7 @@ constexpr size_t kStageBytes = sizeof(FrameState) + sizeof(int32_t) * 3 * kMaxSe
 struct Request {
     int64_t ticket = 0;
     dic_ctx *ref = nullptr;
+    int32_t ref_id = -1;
     dic_image def{};
     std::vector<dic_seed> seeds;
     dic_result out{};
@@ -384,6 +385,7 @@ dic_status dic_server_submit(dic_server *s, int32_t ref_id, const dic_image *def
     Request *r = new Request();
     r->ticket = s->next_ticket++;
     r->ref = c;
+    r->ref_id = ref_id;
     r->def = *def;
     r->seeds.assign(seeds, seeds + nseeds);
     r->out = *out;
@@ -402,13 +404,14 @@ dic_status dic_server_step(dic_server *s, int32_t steps)
     SHIP(hipSetDevice(s->device));
     hipStream_t st = s->stream;
 
-    // ---- admission, FIFO: a request that can never fit fails, one that does not
-    // fit now waits for the active ones to finish
+    // ---- admission, FIFO: a request that cannot fit even beside its own reference
+    // alone fails; one that does not fit now waits (for active requests to finish,
+    // or for the caller to remove references)
     while (!s->waiting.empty() && static_cast<int>(s->active.size()) < s->prm.max_active) {
         Request *r = s->waiting.front();
         const double need = static_cast<double>(request_bytes(r->ref));
         const bool pooled = !s->pool[r->ref].empty();
-        if (!pooled && s->ref_bytes + need > s->prm.hbm_budget_bytes) {
+        if (!pooled && s->ref_size[r->ref_id] + need > s->prm.hbm_budget_bytes) {
             s->waiting.pop_front();
             r->state = 2;
             r->result = DIC_E_NOMEM;

@@ -260,3 +260,33 @@ def test_remove_reference_frees_budget():
     torch.cuda.synchronize()
     _equal({k: v.cpu().numpy() for k, v in out.items()}, first, "re-added")
     srv.close()
+
+
+def test_request_waits_for_room_that_reference_removal_frees():
+    import torch
+    w = synth.workload("c1", size=192)
+    pair = w.pair()
+    roi = torch.from_numpy(np.ascontiguousarray(pair.roi)).cuda()
+    ref = dic.to_device_image(pair.ref)
+    de = dic.to_device_image(pair.deformed)
+    probe = dic.Server(0, max_active=4, hbm_budget_bytes=1e12)
+    probe.add_reference(ref, roi, **w.params())
+    one = probe.stats()["used_bytes"]
+    probe.close()
+    # two references and a little room: a request (about a third of a reference)
+    # fits beside its own reference but not beside both
+    srv = dic.Server(0, max_active=4, hbm_budget_bytes=2.2 * one)
+    a = srv.add_reference(ref, roi, **w.params())
+    b = srv.add_reference(ref, roi, **w.params())
+    t, out = srv.submit(a, de, w.seeds)
+    srv.step(2)
+    assert not srv.poll(t)[0]
+    assert srv.stats()["waiting"] == 1 and srv.stats()["active"] == 0
+    srv.remove_reference(b)
+    for _ in range(500):
+        srv.step(4)
+        if srv.poll(t)[0]:
+            break
+    done, status, _ = srv.poll(t)
+    assert done and status == dic.DIC_OK
+    srv.close()
