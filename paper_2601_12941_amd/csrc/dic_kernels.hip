@@ -983,6 +983,7 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
     __shared__ int prefix[kMaxFrames + 1];
     __shared__ int owned[kMaxFrames + 1];
     __shared__ double cache[NC];      // this subset's reference cache
+    __shared__ float qa[4 * NP];      // the four possible parents' parameters
     __shared__ double pub_p[NP];      // parameters published by the first wavefront
     __shared__ int pub_stop;
     const int nframes = frames.n;
@@ -1034,25 +1035,47 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
         const int ix = node % R.nx, iy = node / R.nx;
         const int xc = h + ix * R.step, yc = h + iy * R.step;
 
-        // ---- everything the subset needs from memory is requested up front; only
-        // the parent's parameters wait for the parent key
+        // ---- the subset's metadata: flag, parent key, the four possible parents'
+        // parameters (the key selects one; reading all four saves a dependent round
+        // trip) and the reference cache.  Small register blocks take the parents'
+        // parameters straight into LDS and load the reference pixels afterwards, which
+        // keeps them at three wavefronts per SIMD; the 16-row block (two wavefronts
+        // either way) requests everything at once into registers.
+        constexpr bool kQaInLds = P <= 12;
         const int8_t rf = R.flag[node];
         const uint64_t key = k > 0 ? F.pkey[node] : 0;
-        // the four possible parents' parameters are read together with the key (the key
-        // only selects one), saving a dependent round trip; indices are clamped to the grid
-        float qa[4][NP];
-        if (k > 0) {
-            const int64_t nb[4] = {static_cast<int64_t>(iy) * R.nx + max(ix - 1, 0),
-                                   static_cast<int64_t>(iy) * R.nx + min(ix + 1, R.nx - 1),
-                                   static_cast<int64_t>(max(iy - 1, 0)) * R.nx + ix,
-                                   static_cast<int64_t>(min(iy + 1, R.ny - 1)) * R.nx + ix};
+        float qr[kQaInLds ? 1 : 4][NP];
+        if constexpr (!kQaInLds) {
+            if (k > 0) {
+                const int64_t nb[4] = {static_cast<int64_t>(iy) * R.nx + max(ix - 1, 0),
+                                       static_cast<int64_t>(iy) * R.nx + min(ix + 1, R.nx - 1),
+                                       static_cast<int64_t>(max(iy - 1, 0)) * R.nx + ix,
+                                       static_cast<int64_t>(min(iy + 1, R.ny - 1)) * R.nx + ix};
 #pragma unroll
-            for (int d = 0; d < 4; ++d)
+                for (int d = 0; d < 4; ++d)
 #pragma unroll
-                for (int j = 0; j < NP; ++j) qa[d][j] = F.p[j * nn + nb[d]];
+                    for (int j = 0; j < NP; ++j) qr[d][j] = F.p[j * nn + nb[d]];
+            }
         }
         __syncthreads();   // the previous subset is done with the LDS cache and window
+        if constexpr (kQaInLds) {
+            if (k > 0 && t < 4 * NP) {
+                const int dd = t / NP, j = t - dd * NP;
+                const int64_t nb = dd == 0 ? static_cast<int64_t>(iy) * R.nx + max(ix - 1, 0)
+                                 : dd == 1 ? static_cast<int64_t>(iy) * R.nx + min(ix + 1, R.nx - 1)
+                                 : dd == 2 ? static_cast<int64_t>(max(iy - 1, 0)) * R.nx + ix
+                                           : static_cast<int64_t>(min(iy + 1, R.ny - 1)) * R.nx + ix;
+                __builtin_amdgcn_global_load_lds(
+                    (const __attribute__((address_space(1))) void *)(F.p + j * nn + nb),
+                    (__attribute__((address_space(3))) void *)(qa), 4, 0, 0);
+            }
+        }
         for (int q = t; q < NC; q += T) cache[q] = R.cache[static_cast<int64_t>(q) * nn + node];
+        if constexpr (kQaInLds) {
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();   // metadata visible to every wavefront
+        }
+        // reference intensities and gradients
         float fb[P], gx[P], gy[P];
 #pragma unroll
         for (int j = 0; j < P; ++j) {
@@ -1064,6 +1087,7 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
                 gy[j] = R.pfy[o];
             }
         }
+        if constexpr (!kQaInLds) __syncthreads();   // cache visible to every wavefront
 
         // ---- initial guess
         double p[NP];
@@ -1080,8 +1104,12 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
             const int sel = dir == 3 ? 0 : (dir == 2 ? 1 : (dir == 1 ? 2 : 3));
             double q[NP];
 #pragma unroll
-            for (int j = 0; j < NP; ++j)
-                q[j] = static_cast<double>(sel == 0 ? qa[0][j] : (sel == 1 ? qa[1][j] : (sel == 2 ? qa[2][j] : qa[3][j])));
+            for (int j = 0; j < NP; ++j) {
+                if constexpr (kQaInLds)
+                    q[j] = static_cast<double>(qa[sel * NP + j]);
+                else
+                    q[j] = static_cast<double>(sel == 0 ? qr[0][j] : (sel == 1 ? qr[1][j] : (sel == 2 ? qr[2][j] : qr[3][j])));
+            }
 #pragma unroll
             for (int j = 0; j < NP; ++j) p[j] = q[j];
             if (!R.guess_copy) {
@@ -1103,7 +1131,6 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
         int status = kMaxIter;
         int iters = 0;
         float zncc_out = 0.0f;
-        __syncthreads();   // cache visible to every wavefront
         if (rf != 0) {
             status = rf;
         } else {
