@@ -559,7 +559,8 @@ def main():
     ap.add_argument("--plain-tps", type=int, default=0, help="threads per subset, plain form (0: autotuned)")
     ap.add_argument("--tile", type=int, default=0, help="LDS window side, batched form (0: autotuned with --tps 0)")
     ap.add_argument("--plain-tile", type=int, default=0, help="LDS window side, plain form")
-    ap.add_argument("--tune-size", type=int, default=1024, help="side of the autotuner's proxy pair")
+    ap.add_argument("--tune-size", type=int, default=0,
+                    help="side of the autotuner's pair (0: the benchmark's own pair)")
     ap.add_argument("--cpu-crop", type=int, default=2048, help="oracle sample window (0 = skip)")
     ap.add_argument("--workload", default="2048", choices=["2048", "gigapixel", "serve", "precision"],
                     help="2048: the 2048^2 batched/plain benchmark; gigapixel: the 32768^2 pair, repeated; "
@@ -614,10 +615,14 @@ def main():
     tuned = {}
     if args.tps == 0 or args.plain_tps == 0:
         from paper_2601_12941_amd import autotune
-        wt = synth.workload("c2", size=args.tune_size)
-        tref, tframes, troi = render_frames(wt, args.batch)
-        proxy = (tref, tframes, troi, wt.seeds)
-        pname = "%d^2 crop of the 2048^2 workload recipe" % args.tune_size
+        if args.tune_size in (0, args.size):
+            proxy = (ref, frames, roi, w.seeds)     # the benchmark's own pair
+            pname = "the %d^2 workload itself" % args.size
+        else:
+            wt = synth.workload("c2", size=args.tune_size)
+            tref, tframes, troi = render_frames(wt, args.batch)
+            proxy = (tref, tframes, troi, wt.seeds)
+            pname = "%d^2 pair of the 2048^2 workload recipe" % args.tune_size
 
         def log(msg):
             print("# " + msg, file=sys.stderr, flush=True)
