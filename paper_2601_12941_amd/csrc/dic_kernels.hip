@@ -915,46 +915,57 @@ __device__ __forceinline__ void lift(const double (&q)[12], double (&Q)[6][6])
     Q[5][0] = 0.0; Q[5][1] = 0.0; Q[5][2] = 0.0; Q[5][3] = 0.0; Q[5][4] = 0.0; Q[5][5] = 1.0;
 }
 
-__device__ __forceinline__ void compose_quadratic(double (&p)[12], const double (&d)[12])
+// The elimination runs on a 6 x 8 working matrix in LDS (M, 48 doubles, one per
+// workgroup): its rows are picked by the pivot search at run time, which in
+// registers would force the whole matrix out to scratch memory.
+__device__ __forceinline__ void compose_quadratic(double (&p)[12], const double (&d)[12], double *M)
 {
-    double Qp[6][6], M[6][8];
-    lift(p, Qp);
     {
         double Qd[6][6];
         lift(d, Qd);
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
 #pragma unroll
-            for (int j = 0; j < 6; ++j) M[i][j] = Qd[j][i];   // transpose
-            M[i][6] = Qp[3][i];
-            M[i][7] = Qp[4][i];
+            for (int j = 0; j < 6; ++j) M[i * 8 + j] = Qd[j][i];   // transpose
         }
     }
+    // right-hand sides: the X and Y rows of Q(p), i.e. (a0, a1, a2, A, B, U) and
+    // (b0, b1, b2, C, D, V) in the monomial order
+    M[0 * 8 + 6] = p[6];  M[1 * 8 + 6] = p[7];  M[2 * 8 + 6] = p[8];
+    M[3 * 8 + 6] = 1.0 + p[2]; M[4 * 8 + 6] = p[3]; M[5 * 8 + 6] = p[0];
+    M[0 * 8 + 7] = p[9];  M[1 * 8 + 7] = p[10]; M[2 * 8 + 7] = p[11];
+    M[3 * 8 + 7] = p[4];  M[4 * 8 + 7] = 1.0 + p[5]; M[5 * 8 + 7] = p[1];
 #pragma unroll
     for (int col = 0; col < 6; ++col) {
         int piv = col;
-        double best = fabs(M[col][col]);
+        double best = fabs(M[col * 8 + col]);
 #pragma unroll
-        for (int r = col + 1; r < 6; ++r)
-            if (fabs(M[r][col]) > best) { best = fabs(M[r][col]); piv = r; }
+        for (int r = col + 1; r < 6; ++r) {
+            const double v = fabs(M[r * 8 + col]);
+            if (v > best) { best = v; piv = r; }
+        }
         if (piv != col) {
 #pragma unroll
-            for (int k = 0; k < 8; ++k) { const double tv = M[col][k]; M[col][k] = M[piv][k]; M[piv][k] = tv; }
+            for (int k = 0; k < 8; ++k) {
+                const double tv = M[col * 8 + k];
+                M[col * 8 + k] = M[piv * 8 + k];
+                M[piv * 8 + k] = tv;
+            }
         }
-        const double inv = 1.0 / M[col][col];
+        const double inv = 1.0 / M[col * 8 + col];
 #pragma unroll
         for (int r = 0; r < 6; ++r) {
             if (r == col) continue;
-            const double fct = M[r][col] * inv;
+            const double fct = M[r * 8 + col] * inv;
 #pragma unroll
-            for (int k = col; k < 8; ++k) M[r][k] -= fct * M[col][k];
+            for (int k = col; k < 8; ++k) M[r * 8 + k] -= fct * M[col * 8 + k];
         }
     }
     double x[6], y[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-        x[i] = M[i][6] / M[i][i];
-        y[i] = M[i][7] / M[i][i];
+        x[i] = M[i * 8 + 6] / M[i * 8 + i];
+        y[i] = M[i * 8 + 7] / M[i * 8 + i];
     }
     p[0] = x[5]; p[1] = y[5];
     p[2] = x[3] - 1.0; p[3] = x[4];
@@ -985,6 +996,7 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
     __shared__ double cache[NC];      // this subset's reference cache
     __shared__ float qa[4 * NP];      // the four possible parents' parameters
     __shared__ double pub_p[NP];      // parameters published by the first wavefront
+    __shared__ double qwork[NP == 12 ? 48 : 1];   // quadratic composition's working matrix
     __shared__ int pub_stop;
     const int nframes = frames.n;
 
@@ -1386,7 +1398,7 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
                         }
                         zncc_out = zn;
                         if constexpr (NP == 6) compose_affine(p, dp);
-                        else compose_quadratic(p, dp);
+                        else compose_quadratic(p, dp, qwork);
                         double nrm = dp[0] * dp[0] + dp[1] * dp[1];
                         {
                             double s1 = 0.0, s2 = 0.0;
