@@ -92,7 +92,8 @@ typedef struct {
                                    or 16 / 32: four / two subsets share one 64-lane wavefront
                                    (affine shape, N <= 16) */
     int32_t tile_side;          /* side of the LDS window of deformed coefficients, in samples:
-                                   0 = automatic (N + 17 rounded up to a multiple of 16), else
+                                   0 = automatic (N + 9: the taps' reach and 3 samples of drift
+                                   room on each side), else
                                    N + 5 .. 96; a warped subset that does not fit reads global memory */
 } dic_params;
 

@@ -21,13 +21,14 @@ CACHE = os.environ.get("DIC_AUTOTUNE_CACHE", os.path.join(_HERE, "autotune_cache
 
 
 def default_tile(N: int) -> int:
-    return ((N + 17 + 15) // 16) * 16
+    return N + 9
 
 
 def candidates(N: int, shape: int = 6):
-    """(threads per subset, tile side) pairs worth timing for subset size N."""
-    tiles = sorted({t for t in (default_tile(N) - 16, default_tile(N), default_tile(N) + 16)
-                    if N + 5 <= t <= 96})
+    """(threads per subset, tile side) pairs worth timing for subset size N: the
+    smallest window (1 sample of drift room per side), the library default (3) and
+    a roomy one (7)."""
+    tiles = sorted({t for t in (N + 5, default_tile(N), N + 17) if N + 5 <= t <= 96})
     out = []
     for tps in (16, 32, 64, 128, 256):
         if tps < 64 and (shape != 6 or N > 16):

@@ -48,27 +48,31 @@ __device__ __forceinline__ int fold(int k, int n)
 }
 
 // Cubic B-spline weights of taps x0-1 .. x0+2 at fraction t (beta3 sampled at
-// t+1, t, t-1, t-2).
+// t+1, t, t-1, t-2), scaled by 6: (1-t)^3, 4 - 6t^2 + 3t^3, the same polynomial
+// at 1-t, and t^3.  The prefilter folds the 1/6 of each axis into the
+// coefficients, so the tensor product of the scaled weights with them is the
+// interpolant itself; the scaling saves the divisions by 6 and lets the mirror
+// symmetry w2(t) = w1(1-t) share the second cubic's form.
 __device__ __forceinline__ void bspline_w(float t, float &w0, float &w1, float &w2, float &w3)
 {
     const float s = 1.0f - t;
     const float t2 = t * t;
-    const float t3 = t2 * t;
-    w0 = s * s * s * (1.0f / 6.0f);
-    w1 = fmaf(0.5f, t3, fmaf(-1.0f, t2, 2.0f / 3.0f));
-    w2 = fmaf(-0.5f, t3, fmaf(0.5f, t2, fmaf(0.5f, t, 1.0f / 6.0f)));
-    w3 = t3 * (1.0f / 6.0f);
+    const float s2 = s * s;
+    w0 = s2 * s;
+    w1 = fmaf(fmaf(3.0f, t, -6.0f), t2, 4.0f);
+    w2 = fmaf(fmaf(3.0f, s, -6.0f), s2, 4.0f);
+    w3 = t2 * t;
 }
 
-// their derivatives with respect to t
+// their derivatives with respect to t, scaled by 6 like the weights
 __device__ __forceinline__ void bspline_dw(float t, float &d0, float &d1, float &d2, float &d3)
 {
     const float s = 1.0f - t;
     const float t2 = t * t;
-    d0 = -0.5f * (s * s);
-    d1 = fmaf(1.5f, t2, -2.0f * t);
-    d2 = fmaf(-1.5f, t2, t + 0.5f);
-    d3 = 0.5f * t2;
+    d0 = -3.0f * (s * s);
+    d1 = fmaf(9.0f, t2, -12.0f * t);
+    d2 = fmaf(-9.0f, t2, fmaf(6.0f, t, 3.0f));
+    d3 = 3.0f * t2;
 }
 
 __device__ __forceinline__ float to_f32(float v) { return v; }
@@ -97,17 +101,19 @@ __device__ __forceinline__ uint32_t ordered_bits(float f)
 }
 
 // Value of the lane chosen by DPP control CTRL (quad_perm, row mirrors), per 32-bit half.
+// (every control used here has a source lane for every lane and the row and bank
+// masks are full, so each lane is written and no previous value needs setting)
 template <int CTRL>
 __device__ __forceinline__ double dpp_read(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
 template <int CTRL>
 __device__ __forceinline__ float dpp_read(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 
 // v + (v of the partner lane) where the partner sits in the other 16-lane row of a row
@@ -230,10 +236,12 @@ struct Columns {
 //   s[0] = sum g',  s[1] = sum g'^2,  s[2] = sum fbar g',
 //   s[3+k] = sum J_k g'  with J = grad f . dW/dp in Eq. (5) order:
 //   [fx, fy, fx dx, fx dy, fy dx, fy dy, fx dx^2, fx dx dy, fx dy^2, fy dx^2, fy dx dy, fy dy^2].
-// g' is the deformed value minus the reference subset mean.
+// g' is the deformed value minus the reference subset mean.  A thread walks
+// the rows of one subset column, so dx is the same for all its pixels: the
+// pass accumulates only the terms without a dx factor, and finish_column
+// multiplies the others out once at the end.
 template <int NP>
-__device__ __forceinline__ void accumulate(float (&s)[3 + NP], float g, float fb, float gx, float gy, float dx,
-                                           float dy)
+__device__ __forceinline__ void accumulate(float (&s)[3 + NP], float g, float fb, float gx, float gy, float dy)
 {
     s[0] = s[0] + g;
     s[1] = fmaf(g, g, s[1]);
@@ -242,18 +250,25 @@ __device__ __forceinline__ void accumulate(float (&s)[3 + NP], float g, float fb
     const float c = gy * g;
     s[3] = s[3] + a;
     s[4] = s[4] + c;
-    s[5] = fmaf(a, dx, s[5]);
     s[6] = fmaf(a, dy, s[6]);
-    s[7] = fmaf(c, dx, s[7]);
     s[8] = fmaf(c, dy, s[8]);
     if constexpr (NP == 12) {
-        const float ax = a * dx, ay = a * dy, cx = c * dx, cy = c * dy;
-        s[9] = fmaf(ax, dx, s[9]);
-        s[10] = fmaf(ax, dy, s[10]);
-        s[11] = fmaf(ay, dy, s[11]);
-        s[12] = fmaf(cx, dx, s[12]);
-        s[13] = fmaf(cx, dy, s[13]);
-        s[14] = fmaf(cy, dy, s[14]);
+        s[11] = fmaf(a * dy, dy, s[11]);
+        s[14] = fmaf(c * dy, dy, s[14]);
+    }
+}
+
+// the dx-weighted sums of one column, from the sums accumulate kept
+template <int NP>
+__device__ __forceinline__ void finish_column(float (&s)[3 + NP], float dx)
+{
+    s[5] = dx * s[3];
+    s[7] = dx * s[4];
+    if constexpr (NP == 12) {
+        s[9] = dx * s[5];
+        s[10] = dx * s[6];
+        s[12] = dx * s[7];
+        s[13] = dx * s[8];
     }
 }
 
@@ -265,6 +280,8 @@ __device__ __forceinline__ void accumulate(float (&s)[3 + NP], float g, float fb
 // mirror-extended input the truncated FIR reproduces the mirror-boundary
 // solution.  Separable: rows into an FP32 scratch array, then columns into the
 // padded coefficient array (padding filled with the mirrored coefficients).
+// The stored coefficients are 1/36 of these (1/6 per pass), to match the
+// interpolation weights, which are 6 times the B-spline's.
 // ---------------------------------------------------------------------------
 constexpr int kFir = 15;
 __constant__ float c_fir[2 * kFir + 1];
@@ -319,8 +336,9 @@ void launch_prefilter(const void *src, int64_t src_pitch_bytes, int pixel, int W
     if (dev < 0 || dev >= 64 || !taps_ready[dev]) {
         float h[2 * kFir + 1];
         const double z = sqrt(3.0) - 2.0;
-        for (int n = -kFir; n <= kFir; ++n) h[n + kFir] = static_cast<float>(sqrt(3.0) * pow(fabs(z), abs(n)) *
-                                                                             ((abs(n) & 1) ? -1.0 : 1.0));
+        // each pass carries the 1/6 of its axis that the scaled interpolation weights leave out
+        for (int n = -kFir; n <= kFir; ++n)
+            h[n + kFir] = static_cast<float>(sqrt(3.0) * pow(fabs(z), abs(n)) * ((abs(n) & 1) ? -1.0 : 1.0) / 6.0);
         (void)hipMemcpyToSymbol(HIP_SYMBOL(c_fir), h, sizeof(h));
         if (dev >= 0 && dev < 64) taps_ready[dev] = true;
     }
@@ -467,7 +485,7 @@ __global__ __launch_bounds__(T) void k_ref_nodes(RefView R, double *cache, int8_
                 const float fb = R.pf[o] - fm32;
                 const float gx = R.pfx[o], gy = R.pfy[o];
                 const float dyf = fmaf(static_cast<float>(j), dyR, dy0);
-                accumulate<NP>(s, fb, fb, gx, gy, dxf, dyf);
+                accumulate<NP>(s, fb, fb, gx, gy, dyf);
                 double J[NP];
                 steepest<NP>(J, gx, gy, dxf, dyf);
                 int q = NP;
@@ -482,6 +500,7 @@ __global__ __launch_bounds__(T) void k_ref_nodes(RefView R, double *cache, int8_
                 }
             }
         }
+        finish_column<NP>(s, dxf);
         double va[3 + NP];
 #pragma unroll
         for (int i = 0; i < 3 + NP; ++i) va[i] = static_cast<double>(s[i]);
@@ -977,10 +996,11 @@ __device__ __forceinline__ void compose_quadratic(double (&p)[12], const double 
 // ---------------------------------------------------------------------------
 // One frontier wave: every subset of wave k of every frame.
 // ---------------------------------------------------------------------------
-// Register blocks of at most 4 rows fit three wavefronts per SIMD without spilling;
-// ask the compiler for that occupancy there (the latency-bound single-frame form
-// runs them).
-template <int NP, int P> constexpr int wave_occupancy_hint() { return (NP == 6 && P <= 4) ? 3 : 1; }
+// Affine register blocks of at most 4 rows fit three wavefronts per SIMD without
+// spilling, quadratic ones of at most 8 rows two (a few bytes of the FP64 tail
+// spill for 8 rows, far cheaper than running one wavefront per SIMD); ask the
+// compiler for that occupancy there.
+template <int NP, int P> constexpr int wave_occupancy_hint() { return NP == 6 ? (P <= 4 ? 3 : 1) : (P <= 8 ? 2 : 1); }
 
 template <int NP, int T, int P, bool F64>
 __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(const FrameTable frames, int step)
@@ -1175,7 +1195,7 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
                     if constexpr (NP == 12) {
                         // the box is conservative for the quadratic shape: check every point
                         int any = 0;
-#pragma unroll
+#pragma unroll 1
                         for (int j = 0; j < P; ++j) {
                             if (j < L.jmax) {
                                 const double dx = dxf, dy = static_cast<double>(L.r0 - h + L.R * j);
@@ -1299,7 +1319,7 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
                             // avoids a quarter-rate integer multiply per pixel
                             const int off = static_cast<int>(fmaf(fy0, tsf, fx0));
                             const float g = interp16(tb + off, ts, wx0, wx1, wx2, wx3, wy0, wy1, wy2, wy3);
-                            accumulate<NP>(s, on ? g - fm32 : 0.0f, fb[j], gx[j], gy[j], dxf, dy);
+                            accumulate<NP>(s, on ? g - fm32 : 0.0f, fb[j], gx[j], gy[j], dy);
                         }
                     }
                 } else {
@@ -1336,9 +1356,10 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
                                 gxj = gx[q];
                                 gyj = gy[q];
                             }
-                        accumulate<NP>(s, g - fm32, fbj, gxj, gyj, dx, dy);
+                        accumulate<NP>(s, g - fm32, fbj, gxj, gyj, dy);
                     }
                 }
+                finish_column<NP>(s, dxf);
                 // ---- reduce; the rest of the iteration (checks, increment, composition,
                 // convergence) is scalar FP64 work that the first wavefront does alone and
                 // publishes through LDS, so the other wavefronts do not repeat it
@@ -1531,7 +1552,7 @@ __global__ __launch_bounds__(64) void k_ref_nodes_packed(RefView R, double *cach
                 const float fb = R.pf[o] - fm32;
                 const float gx = R.pfx[o], gy = R.pfy[o];
                 const float dyf = fmaf(static_cast<float>(j), dyR, dy0);
-                accumulate<NP>(s, fb, fb, gx, gy, dxf, dyf);
+                accumulate<NP>(s, fb, fb, gx, gy, dyf);
                 double J[NP];
                 steepest<NP>(J, gx, gy, dxf, dyf);
                 int q = NP;
@@ -1546,6 +1567,7 @@ __global__ __launch_bounds__(64) void k_ref_nodes_packed(RefView R, double *cach
                 }
             }
         }
+        finish_column<NP>(s, dxf);
         double va[3 + NP];
 #pragma unroll
         for (int i = 0; i < 3 + NP; ++i) va[i] = seg_allreduce<LS>(static_cast<double>(s[i]));
@@ -1758,10 +1780,11 @@ __global__ __launch_bounds__(64) void k_wave_packed(const FrameTable frames, int
                                       : interp16(static_cast<const float *>(F.dcoef) + go, F.dpitch, wx0, wx1, wx2,
                                                  wx3, wy0, wy1, wy2, wy3);
                         }
-                        accumulate<NP>(s, gv - fm32, fb[j], gx[j], gy[j], dxf, dy);
+                        accumulate<NP>(s, gv - fm32, fb[j], gx[j], gy[j], dy);
                     }
                 }
             }
+            finish_column<NP>(s, dxf);
             // segmented sums over each group's lanes (every lane takes part)
             Acc v[NS];
 #pragma unroll
@@ -1905,8 +1928,10 @@ int pixels_per_thread(int N, int T)
 
 int tile_side(int N)
 {
-    // the warped subset plus 4 taps plus room to drift: 17 px beyond N, rounded to 16
-    return ((N + 17 + 15) / 16) * 16;
+    // the warped subset, its 4-tap reach (3 samples) and 3 samples of room to drift
+    // on each side; a window that no longer holds the taps is restaged, and one the
+    // warped subset outgrows sends the subset to the global-memory path
+    return N + 9;
 }
 
 // One launch for every frame of F at launch step `step`.  All frames must use the

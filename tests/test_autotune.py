@@ -3,11 +3,11 @@ from paper_2601_12941_amd import autotune
 
 
 def test_default_tile_matches_the_library_rule():
-    # N + 17 rounded up to a multiple of 16
-    assert autotune.default_tile(21) == 48
-    assert autotune.default_tile(31) == 48
-    assert autotune.default_tile(41) == 64
-    assert autotune.default_tile(51) == 80
+    # N + 9: the 3-sample reach of the taps and 3 samples of drift room per side
+    assert autotune.default_tile(21) == 30
+    assert autotune.default_tile(31) == 40
+    assert autotune.default_tile(41) == 50
+    assert autotune.default_tile(51) == 60
 
 
 def test_candidates_respect_the_window_and_wavefront_limits():
@@ -20,8 +20,8 @@ def test_candidates_respect_the_window_and_wavefront_limits():
             assert N + 5 <= ts <= 96
     assert {t for t, _ in autotune.candidates(15)} == {16, 32, 64, 128, 256}
     assert {t for t, _ in autotune.candidates(15, shape=12)} == {64, 128, 256}
-    assert sorted({s for _, s in autotune.candidates(31)}) == [48, 64]
-    assert sorted({s for _, s in autotune.candidates(63)}) == [80, 96]
+    assert sorted({s for _, s in autotune.candidates(31)}) == [36, 40, 48]
+    assert sorted({s for _, s in autotune.candidates(63)}) == [68, 72, 80]
 
 
 def test_cache_round_trip(tmp_path, monkeypatch):
