@@ -211,8 +211,27 @@ def gigapixel(args, repeats=6, samples=24):
     torch.cuda.synchronize()
     free0, total = torch.cuda.mem_get_info()
     eng = dic.Engine(0)
+    # launch shape: time each candidate on the pair itself (two correlations each)
+    shapes = [(args.giga_tps, args.giga_tile)] if args.giga_tps else \
+        [(tps, w.N + dt) for tps in (128, 256) for dt in (5, 9)]
+    sweep = []
+    if len(shapes) > 1:
+        for tps, ts in shapes:
+            eng.set_reference(d_ref, d_roi, **w.params(), threads_per_subset=tps, tile_side=ts)
+            tt = []
+            for _ in range(2):
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                eng.correlate(d_def, w.seeds)
+                torch.cuda.synchronize()
+                tt.append(time.perf_counter() - t1)
+            sweep.append({"threads_per_subset": tps, "tile_side": ts, "ms": min(tt) * 1e3})
+            note("shape %d threads, window %d: %.1f ms" % (tps, ts, min(tt) * 1e3))
+    best = min(sweep, key=lambda r: r["ms"]) if sweep else {"threads_per_subset": shapes[0][0],
+                                                            "tile_side": shapes[0][1]}
     t0 = time.perf_counter()
-    eng.set_reference(d_ref, d_roi, **w.params())
+    eng.set_reference(d_ref, d_roi, **w.params(), threads_per_subset=best["threads_per_subset"],
+                      tile_side=best["tile_side"])
     torch.cuda.synchronize()
     t_ref = time.perf_counter() - t0
     lat = []
@@ -253,7 +272,8 @@ def gigapixel(args, repeats=6, samples=24):
     lat_ms = np.array(lat) * 1e3
     rec = {"workload": "32768x32768 u8 speckle, shift (3.41, -7.92) + Gaussian bump, subset 41, step 20, 16 seeds",
            "nodes": st["nodes"], "active": st["active"], "converged": int(conv.sum()), "waves": st["waves"],
-           "threads_per_subset": st["threads_per_subset"], "repeats": repeats,
+           "threads_per_subset": st["threads_per_subset"], "tile_side": best["tile_side"],
+           "launch_shape_sweep": sweep, "repeats": repeats,
            "latency_ms_p50": float(np.percentile(lat_ms, 50)), "latency_ms_p99": float(np.percentile(lat_ms, 99)),
            "converged_subsets_per_s": float(conv.sum() / np.median(lat)), "set_reference_ms": t_ref * 1e3,
            "render_s": t_render, "sampled_parity": {"nodes": used, "max_duv_px": float(max(errs)) if errs else None,
@@ -566,6 +586,9 @@ def main():
                     help="2048: the 2048^2 batched/plain benchmark; gigapixel: the 32768^2 pair, repeated; "
                          "serve: the serving mix")
     ap.add_argument("--precision-size", type=int, default=2048, help="precision: image side")
+    ap.add_argument("--giga-tps", type=int, default=0,
+                    help="gigapixel: threads per subset (0: time 128/256 threads x windows N+5/N+9 on the pair)")
+    ap.add_argument("--giga-tile", type=int, default=0, help="gigapixel: LDS window side with --giga-tps")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: seconds of Poisson arrivals")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: requests per second")
     ap.add_argument("--max-active", type=int, default=48, help="serve: requests on the device at once")
