@@ -79,8 +79,11 @@ def profiled_traffic():
     return rec["traffic_bytes_per_launch"] if rec.get("source_sha256") == sha else None
 
 
-PROFILE_BENCH = "bench.py --steps 2 --warmup 1 --latency-runs 3 --cpu-crop 0 --tps 64 --tile 48 --plain-tps 128 --plain-tile 48"
-PMC_BENCH = "bench.py --steps 1 --warmup 0 --latency-runs 1 --cpu-crop 0 --tps 64 --tile 48 --plain-tps 128 --plain-tile 48"
+# the launch shapes the autotuner picks on the 2048^2 workload, fixed for the profiled runs
+PROFILE_SHAPES = dict(tps=64, tile=36, plain_tps=128, plain_tile=36)
+_SHAPE_ARGS = "--tps %(tps)d --tile %(tile)d --plain-tps %(plain_tps)d --plain-tile %(plain_tile)d" % PROFILE_SHAPES
+PROFILE_BENCH = "bench.py --steps 2 --warmup 1 --latency-runs 3 --cpu-crop 0 " + _SHAPE_ARGS
+PMC_BENCH = "bench.py --steps 1 --warmup 0 --latency-runs 1 --cpu-crop 0 " + _SHAPE_ARGS
 
 
 def _short(name):
@@ -100,9 +103,10 @@ def summarize_trace(d, out):
              "```", "rocprofv3 --kernel-trace --stats -f csv -d <out> -o run -- python3 " + PROFILE_BENCH, "```", "",
              "Summary written by `python bench.py --summarize-trace <out> --summary-out <this file>`.", "",
              "Workload: 2048x2048 u16 speckle, sinusoidal u, subset 31, step 2, affine (1 010 025 active subsets per "
-             "frame, 1005 waves). Batched form: 16 frames per launch, 64 threads per subset, 48-sample window "
-             "(`k_wave<6, 64, 16, true>`); plain form: one frame per call, 128 threads per subset "
-             "(`k_wave<6, 128, 8, true>`); the launch shapes the autotuner picks on this workload.", "",
+             "frame, 1005 waves). Batched form: 16 frames per launch, %d threads per subset, %d-sample window; "
+             "plain form: one frame per call, %d threads per subset, %d-sample window; the launch shapes the "
+             "autotuner picks on this workload." % (PROFILE_SHAPES["tps"], PROFILE_SHAPES["tile"],
+                                                     PROFILE_SHAPES["plain_tps"], PROFILE_SHAPES["plain_tile"]), "",
              "| Kernel | Calls | Total ms | Average us | % | Min us | Max us |", "|---|---|---|---|---|---|---|"]
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:14]:
         lines.append("| `%s` | %s | %.1f | %.1f | %.2f | %.1f | %.1f |" % (

@@ -1002,6 +1002,10 @@ __device__ __forceinline__ void compose_quadratic(double (&p)[12], const double 
 // compiler for that occupancy there.
 template <int NP, int P> constexpr int wave_occupancy_hint() { return NP == 6 ? (P <= 4 ? 3 : 1) : (P <= 8 ? 2 : 1); }
 
+// Row software pipelining needs 16 more registers; blocks of 12 and 16 rows run two
+// wavefronts per SIMD either way, smaller ones would lose their third.
+template <int P> constexpr bool kPipelineRows() { return P >= 12; }
+
 template <int NP, int T, int P, bool F64>
 __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(const FrameTable frames, int step)
 {
@@ -1299,9 +1303,35 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
                     // rows per thread of this subset (a launch may mix subset sizes, P is
                     // the largest); uniform across the workgroup
                     const int JM = __builtin_amdgcn_readfirstlane((N + L.R - 1) / L.R);
-#pragma unroll
-                    for (int j = 0; j < P; ++j) {
-                        if (j < JM) {
+                    auto pixel_row = [&](int j) {
+                        const bool on = j < L.jmax;
+                        const float dy = on ? fmaf(static_cast<float>(j), dyR, dy0) : dyl;
+                        float X = fmaf(A2, dy, Xc);
+                        float Y = fmaf(B2, dy, Yc);
+                        if constexpr (NP == 12) {
+                            const float xx = dxf * dxf, xy = dxf * dy, yy = dy * dy;
+                            X = fmaf(Q[2], yy, fmaf(Q[1], xy, fmaf(Q[0], xx, X)));
+                            Y = fmaf(Q[5], yy, fmaf(Q[4], xy, fmaf(Q[3], xx, Y)));
+                        }
+                        const float fx0 = floorf(X), fy0 = floorf(Y);
+                        float wx0, wx1, wx2, wx3, wy0, wy1, wy2, wy3;
+                        bspline_w(X - fx0, wx0, wx1, wx2, wx3);
+                        bspline_w(Y - fy0, wy0, wy1, wy2, wy3);
+                        // tap offset in the window: exact in FP32 (|values| < 2^24), which
+                        // avoids a quarter-rate integer multiply per pixel
+                        const int off = static_cast<int>(fmaf(fy0, tsf, fx0));
+                        const float g = interp16(tb + off, ts, wx0, wx1, wx2, wx3, wy0, wy1, wy2, wy3);
+                        // a weight rather than a select: the row is then computed on every
+                        // lane instead of under a branch, which keeps the rows in one block
+                        accumulate<NP>(s, (g - fm32) * (on ? 1.0f : 0.0f), fb[j], gx[j], gy[j], dy);
+                    };
+                    if (kPipelineRows<P>() && JM == P) {
+                        // every row of the register block is in use (the usual case): one
+                        // straight-line block, software-pipelined by a row: the 16 window
+                        // reads of row j+1 are issued before row j is computed, so their
+                        // latency hides behind that arithmetic
+                        float tap[2][16], frx[2], fry[2], dyv[2];
+                        auto fetch_row = [&](int j, int b) {
                             const bool on = j < L.jmax;
                             const float dy = on ? fmaf(static_cast<float>(j), dyR, dy0) : dyl;
                             float X = fmaf(A2, dy, Xc);
@@ -1312,15 +1342,39 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
                                 Y = fmaf(Q[5], yy, fmaf(Q[4], xy, fmaf(Q[3], xx, Y)));
                             }
                             const float fx0 = floorf(X), fy0 = floorf(Y);
+                            frx[b] = X - fx0;
+                            fry[b] = Y - fy0;
+                            dyv[b] = dy;
+                            const float *q = tb + static_cast<int>(fmaf(fy0, tsf, fx0));
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                                for (int c = 0; c < 4; ++c) tap[b][4 * r + c] = q[r * ts + c];
+                        };
+                        fetch_row(0, 0);
+#pragma unroll
+                        for (int j = 0; j < P; ++j) {
+                            const int b = j & 1;
+                            if (j + 1 < P) fetch_row(j + 1, b ^ 1);
                             float wx0, wx1, wx2, wx3, wy0, wy1, wy2, wy3;
-                            bspline_w(X - fx0, wx0, wx1, wx2, wx3);
-                            bspline_w(Y - fy0, wy0, wy1, wy2, wy3);
-                            // tap offset in the window: exact in FP32 (|values| < 2^24), which
-                            // avoids a quarter-rate integer multiply per pixel
-                            const int off = static_cast<int>(fmaf(fy0, tsf, fx0));
-                            const float g = interp16(tb + off, ts, wx0, wx1, wx2, wx3, wy0, wy1, wy2, wy3);
-                            accumulate<NP>(s, on ? g - fm32 : 0.0f, fb[j], gx[j], gy[j], dy);
+                            bspline_w(frx[b], wx0, wx1, wx2, wx3);
+                            bspline_w(fry[b], wy0, wy1, wy2, wy3);
+                            const float *v = tap[b];
+                            const float r0 = fmaf(wx3, v[3], fmaf(wx2, v[2], fmaf(wx1, v[1], wx0 * v[0])));
+                            const float r1 = fmaf(wx3, v[7], fmaf(wx2, v[6], fmaf(wx1, v[5], wx0 * v[4])));
+                            const float r2 = fmaf(wx3, v[11], fmaf(wx2, v[10], fmaf(wx1, v[9], wx0 * v[8])));
+                            const float r3 = fmaf(wx3, v[15], fmaf(wx2, v[14], fmaf(wx1, v[13], wx0 * v[12])));
+                            const float g = fmaf(wy3, r3, fmaf(wy2, r2, fmaf(wy1, r1, wy0 * r0)));
+                            const bool on = j < L.jmax;
+                            accumulate<NP>(s, (g - fm32) * (on ? 1.0f : 0.0f), fb[j], gx[j], gy[j], dyv[b]);
                         }
+                    } else if (JM == P) {
+#pragma unroll
+                        for (int j = 0; j < P; ++j) pixel_row(j);
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < P; ++j)
+                            if (j < JM) pixel_row(j);
                     }
                 } else {
                     // taps straight from global memory (a window that does not fit)
