@@ -103,10 +103,11 @@ def summarize_trace(d, out):
              "```", "rocprofv3 --kernel-trace --stats -f csv -d <out> -o run -- python3 " + PROFILE_BENCH, "```", "",
              "Summary written by `python bench.py --summarize-trace <out> --summary-out <this file>`.", "",
              "Workload: 2048x2048 u16 speckle, sinusoidal u, subset 31, step 2, affine (1 010 025 active subsets per "
-             "frame, 1005 waves). Batched form: 16 frames per launch, %d threads per subset, %d-sample window; "
-             "plain form: one frame per call, %d threads per subset, %d-sample window; the launch shapes the "
-             "autotuner picks on this workload." % (PROFILE_SHAPES["tps"], PROFILE_SHAPES["tile"],
-                                                     PROFILE_SHAPES["plain_tps"], PROFILE_SHAPES["plain_tile"]), "",
+             "frame, 1005 waves). Batched form: 16 frames per launch, %d threads per subset, %d-sample window "
+             "(the autotuner's pick on this workload); plain form: one frame per call, %d threads per subset, "
+             "%d-sample window (64 and 128 threads tie within 1%% for the plain form)." % (
+                 PROFILE_SHAPES["tps"], PROFILE_SHAPES["tile"], PROFILE_SHAPES["plain_tps"],
+                 PROFILE_SHAPES["plain_tile"]), "",
              "| Kernel | Calls | Total ms | Average us | % | Min us | Max us |", "|---|---|---|---|---|---|---|"]
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:14]:
         lines.append("| `%s` | %s | %.1f | %.1f | %.2f | %.1f | %.1f |" % (
