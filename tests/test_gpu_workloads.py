@@ -14,15 +14,35 @@ from gpu_common import compare, gpu_run, oracle_run
 pytestmark = pytest.mark.gpu
 
 
-def test_sine_field_12bit_parity():
-    # 12-bit speckle, u = 0.5 sin(2 pi x / lambda(y)) with lambda 10..300 px over
-    # the image height, subset 31, step 2
+@pytest.fixture(scope="module")
+def c2_512():
     w = synth.workload("c2", size=512)
     pair = w.pair()
-    g, _ = gpu_run(pair, w)
-    o = oracle_run(pair, w)
+    return w, pair, oracle_run(pair, w)
+
+
+# (threads per subset, window side): the library default (128 threads, 8-row
+# register block), and the benchmark's batched shape (64 threads, 16-row block,
+# the software-pipelined pixel loop, the smallest window)
+@pytest.mark.parametrize("shape_args", [{}, dict(threads_per_subset=64, tile_side=36)])
+def test_sine_field_12bit_parity(c2_512, shape_args):
+    # 12-bit speckle, u = 0.5 sin(2 pi x / lambda(y)) with lambda 10..300 px over
+    # the image height, subset 31, step 2
+    w, pair, o = c2_512
+    g, _ = gpu_run(pair, w, **shape_args)
     compare(g, o)
     assert g["stats"]["seed_du"] == int(o["seed_nodes"][0, 1]) and g["stats"]["seed_dv"] == int(o["seed_nodes"][0, 2])
+
+
+@pytest.mark.parametrize("N, shape, tps", [(23, 6, 64), (35, 12, 128)])
+def test_twelve_row_blocks_parity(N, shape, tps):
+    # subsets that fill a 12-row register block exactly (the software-pipelined
+    # pixel loop): 23 pixels at 64 threads (affine), 35 at 128 threads (quadratic)
+    w = synth.workload("c3", size=384, N=N, shape=shape)
+    pair = w.pair()
+    g, _ = gpu_run(pair, w, threads_per_subset=tps)
+    o = oracle_run(pair, w)
+    compare(g, o, npar=shape)
 
 
 @pytest.mark.parametrize("N", [21, 41])
@@ -177,7 +197,7 @@ def test_full_size_2048_sampled_parity():
     import torch
     w = synth.workload("c2")
     pair = w.pair()
-    g, _ = gpu_run(pair, w)
+    g, _ = gpu_run(pair, w, threads_per_subset=64, tile_side=36)
     st = g["stats"]
     assert st["waves"] > 900 and st["converged"] > 0.99 * st["active"]
     rng = np.random.default_rng(7)
