@@ -1002,9 +1002,9 @@ __device__ __forceinline__ void compose_quadratic(double (&p)[12], const double 
 // compiler for that occupancy there.
 template <int NP, int P> constexpr int wave_occupancy_hint() { return NP == 6 ? (P <= 4 ? 3 : 1) : (P <= 8 ? 2 : 1); }
 
-// Row software pipelining needs 16 more registers; blocks of 12 and 16 rows run two
+// Row software pipelining needs 16 more registers; blocks of 11 to 16 rows run two
 // wavefronts per SIMD either way, smaller ones would lose their third.
-template <int P> constexpr bool kPipelineRows() { return P >= 12; }
+template <int P> constexpr bool kPipelineRows() { return P >= 11; }
 
 template <int NP, int T, int P, bool F64>
 __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(const FrameTable frames, int step)
@@ -1964,21 +1964,27 @@ static void wave_inst(const FrameTable &F, int step, bool f64, int max_ts, int g
 
 // Rows per thread for subset size N at T threads (column-per-thread layout,
 // R = T div N rows per pass): the smallest supported register block holding
-// ceil(N / R) rows; -1 if T < N or none is large enough.
+// ceil(N / R) rows; -1 if T < N or none is large enough.  Besides the powers of
+// two and 12, the 14-row block at 128 threads and the 11-row block at 256 are
+// exact fits for subsets of 41 and 51 pixels (full blocks take the
+// software-pipelined pixel loop).
 int pixels_per_thread(int N, int T)
 {
     if (T < N) return -1;
     const int R = T / N;
     const int need = (N + R - 1) / R;
-    const int opts[] = {2, 4, 8, 12, 16};
-    for (int o : opts)
+    const int opts[] = {2, 4, 8, 11, 12, 14, 16};
+    for (int o : opts) {
+        if ((o == 14 && T != 128) || (o == 11 && T != 256)) continue;
         if (o >= need) return o;
+    }
     return -1;
 }
 
 #define DIC_TP_CASES(NP, X)                                                                                           \
     X(NP, 64, 4) X(NP, 64, 8) X(NP, 64, 12) X(NP, 64, 16) X(NP, 128, 2) X(NP, 128, 4) X(NP, 128, 8) X(NP, 128, 12)    \
-    X(NP, 128, 16) X(NP, 256, 2) X(NP, 256, 4) X(NP, 256, 8) X(NP, 256, 12) X(NP, 256, 16)
+    X(NP, 128, 14) X(NP, 128, 16) X(NP, 256, 2) X(NP, 256, 4) X(NP, 256, 8) X(NP, 256, 11) X(NP, 256, 12)            \
+    X(NP, 256, 16)
 
 int tile_side(int N)
 {

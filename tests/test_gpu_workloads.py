@@ -34,10 +34,11 @@ def test_sine_field_12bit_parity(c2_512, shape_args):
     assert g["stats"]["seed_du"] == int(o["seed_nodes"][0, 1]) and g["stats"]["seed_dv"] == int(o["seed_nodes"][0, 2])
 
 
-@pytest.mark.parametrize("N, shape, tps", [(23, 6, 64), (35, 12, 128)])
-def test_twelve_row_blocks_parity(N, shape, tps):
-    # subsets that fill a 12-row register block exactly (the software-pipelined
-    # pixel loop): 23 pixels at 64 threads (affine), 35 at 128 threads (quadratic)
+@pytest.mark.parametrize("N, shape, tps", [(23, 6, 64), (35, 12, 128), (41, 6, 128), (51, 6, 256), (51, 12, 256)])
+def test_pipelined_blocks_parity(N, shape, tps):
+    # subsets that fill an 11-, 12- or 14-row register block exactly (the
+    # software-pipelined pixel loop): 23 pixels at 64 threads and 35 at 128 (12
+    # rows), 41 at 128 (14 rows), 51 at 256 (11 rows), affine and quadratic
     w = synth.workload("c3", size=384, N=N, shape=shape)
     pair = w.pair()
     g, _ = gpu_run(pair, w, threads_per_subset=tps)
