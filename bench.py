@@ -475,7 +475,12 @@ def serve(args):
         if inflight:
             srv.step(args.chunk)
             ss = srv.stats()
-            if ss["waiting"] > 0 and ss["active"] < args.max_active:
+            # requests that finished in this step leave free slots that the next step's
+            # admission fills, so a waiting request beside a free slot is held by the
+            # budget only once the used bytes are within one request's scratch of it
+            # (below 1 GB on this mix: a 4096^2 window at step 1 needs 0.4 GB)
+            if (ss["waiting"] > 0 and ss["active"] < args.max_active
+                    and ss["used_bytes"] > args.budget_gb * 1e9 - 1e9):
                 # admission is held by the budget: release the least recently used idle reference
                 idle = [k for k, v in resident.items() if inuse[v] == 0]
                 if idle:
@@ -598,7 +603,8 @@ def main():
     ap.add_argument("--duration", type=float, default=60.0, help="serve: seconds of Poisson arrivals")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: requests per second")
     ap.add_argument("--max-active", type=int, default=48, help="serve: requests on the device at once")
-    ap.add_argument("--budget-gb", type=float, default=170.0, help="serve: library HBM budget")
+    ap.add_argument("--budget-gb", type=float, default=230.0,
+                    help="serve: library HBM budget (of the 288 GB; the rest holds the rendered frames and outputs)")
     ap.add_argument("--chunk", type=int, default=8, help="serve: launch steps per server call")
     ap.add_argument("--parity-samples", type=int, default=8, help="serve: requests checked against the oracle")
     ap.add_argument("--summarize-trace", metavar="DIR", help="write the kernel-trace summary of a rocprofv3 run")
