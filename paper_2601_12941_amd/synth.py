@@ -23,6 +23,7 @@ import dataclasses
 import math
 import os
 import subprocess
+import threading
 from typing import Callable, Optional
 
 import numpy as np
@@ -72,20 +73,32 @@ _LARGE = 1 << 24          # pixels above which the C renderer and chunked finish
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
 
+_speckle = None
+_speckle_lock = threading.Lock()
+
+
 def _speckle_lib():
-    """Compile (if needed) and load the OpenMP blob renderer used for large images."""
-    src = os.path.join(_HERE, "speckle_render.c")
-    lib = os.path.join(_HERE, "libspeckle.so")
-    if not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
-        tmp = lib + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-o", tmp, src, "-lm"])
-        os.replace(tmp, lib)
-    L = ctypes.CDLL(lib)
-    dp = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
-    L.speckle_render.argtypes = [np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS"), ctypes.c_long,
-                                 ctypes.c_long, dp, dp, dp, dp, np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS"),
-                                 ctypes.c_long, ctypes.c_double, ctypes.c_long]
-    return L
+    """Compile (if needed) and load the OpenMP blob renderer used for large images.
+    Callers may render from several threads: the first one builds and loads the
+    library under a lock, the others reuse it."""
+    global _speckle
+    with _speckle_lock:
+        if _speckle is not None:
+            return _speckle
+        src = os.path.join(_HERE, "speckle_render.c")
+        lib = os.path.join(_HERE, "libspeckle.so")
+        if not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
+            tmp = lib + ".tmp%d" % os.getpid()
+            subprocess.check_call(["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-o", tmp, src, "-lm"])
+            os.replace(tmp, lib)
+        L = ctypes.CDLL(lib)
+        dp = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+        L.speckle_render.argtypes = [np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS"), ctypes.c_long,
+                                     ctypes.c_long, dp, dp, dp, dp,
+                                     np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS"), ctypes.c_long,
+                                     ctypes.c_double, ctypes.c_long]
+        _speckle = L
+        return L
 
 
 def _render_blobs_large(W: int, H: int, X, Y, S, A) -> np.ndarray:
