@@ -68,16 +68,14 @@ def cpu_baseline(ref, deformed, roi, w, crop):
 
 def profiled_traffic():
     """HBM bytes per batched k_wave launch from the committed FETCH_SIZE / WRITE_SIZE
-    counter runs, if they were taken on the kernel source that is built now."""
-    import hashlib
+    counter runs, if they were taken on the kernel source and compile flags built now."""
+    from paper_2601_12941_amd import build
     rec_path = os.path.join(ROOT, "profiles", "k_wave_2048_batched_traffic.json")
-    src = os.path.join(ROOT, "paper_2601_12941_amd", "csrc", "dic_kernels.hip")
     try:
         rec = json.load(open(rec_path))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except OSError:
         return None
-    return rec["traffic_bytes_per_launch"] if rec.get("source_sha256") == sha else None
+    return rec["traffic_bytes_per_launch"] if rec.get("kernel_build_sha256") == build.kernel_build_id() else None
 
 
 # the launch shapes the autotuner picks on the 2048^2 workload, fixed for the profiled runs
@@ -95,10 +93,10 @@ def _short(name):
 def summarize_trace(d, out):
     """profiles/*.md from a rocprofv3 --kernel-trace --stats directory."""
     import csv
-    import hashlib
     stats = next(os.path.join(r, f) for r, _, fs in os.walk(d) for f in fs if f.endswith("kernel_stats.csv"))
     rows = list(csv.DictReader(open(stats)))
-    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2601_12941_amd", "csrc", "dic_kernels.hip"), "rb").read())
+    from paper_2601_12941_amd import build
+    kid = build.kernel_build_id()
     lines = ["# k_wave on the 2048^2 workload: rocprofv3 kernel trace", "",
              "Command (from the repository root on the MI355X box; rocprofv3 run from /tmp with TMPDIR=/tmp):", "",
              "```", "rocprofv3 --kernel-trace --stats -f csv -d <out> -o run -- python3 " + PROFILE_BENCH, "```", "",
@@ -117,8 +115,9 @@ def summarize_trace(d, out):
     lines += ["", "The batched-form k_wave average above is the launch duration `bench.py` measures live with HIP events "
               "(`roofline.avg_launch_us`; the live figure spans back-to-back launches, so it includes the few-microsecond "
               "gaps between them).",
-              "Kernel source at the time of this profile: sha256 `%s` of `paper_2601_12941_amd/csrc/dic_kernels.hip`."
-              % sha.hexdigest()]
+              "Kernel build at the time of this profile: sha256 `%s` of `paper_2601_12941_amd/csrc/dic_kernels.hip` "
+              "and its compile flags (`build.kernel_build_id()`)."
+              % kid]
     open(out, "w").write("\n".join(lines) + "\n")
     print("wrote", out)
 
@@ -128,7 +127,6 @@ def summarize_pmc(fetch_dir, write_dir, cfetch_dir, cwrite_dir, out_md, out_json
     256 MiB device copy; writes the summary table and the per-launch traffic of
     the batched k_wave that bench.py reports."""
     import csv
-    import hashlib
 
     def per_kernel(d, counter):
         f = next(os.path.join(r, x) for r, _, fs in os.walk(d) for x in fs if x.endswith("counter_collection.csv"))
@@ -145,7 +143,8 @@ def summarize_pmc(fetch_dir, write_dir, cfetch_dir, cwrite_dir, out_md, out_json
     cw = max(per_kernel(cwrite_dir, "WRITE_SIZE").values(), key=lambda v: v[0])[0]
     ff, wf = copy_bytes / 1024.0 / cf, copy_bytes / 1024.0 / cw
     fe, wr = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
-    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2601_12941_amd", "csrc", "dic_kernels.hip"), "rb").read())
+    from paper_2601_12941_amd import build
+    kid = build.kernel_build_id()
     lines = ["# k_wave on the 2048^2 workload: HBM-side byte counters", "",
              "Commands (each a separate pass; rocprofv3 run from /tmp with TMPDIR=/tmp):", "", "```",
              "rocprofv3 --pmc FETCH_SIZE -f csv -d <fetch> -o run -- python3 " + PMC_BENCH,
@@ -164,9 +163,9 @@ def summarize_pmc(fetch_dir, write_dir, cfetch_dir, cwrite_dir, out_md, out_json
     kb = "k_wave<6, 64, 16, true>"
     fetch_b = fe[kb][0] * 1024 * ff
     write_b = wr[kb][0] * 1024 * wf
-    lines += ["", "Kernel source at the time of these counters: sha256 `%s`." % sha.hexdigest()]
+    lines += ["", "Kernel build at the time of these counters: sha256 `%s` of the source and its compile flags." % kid]
     open(out_md, "w").write("\n".join(lines) + "\n")
-    json.dump({"kernel": kb + " (batched form, 16 frames per launch)", "source_sha256": sha.hexdigest(),
+    json.dump({"kernel": kb + " (batched form, 16 frames per launch)", "kernel_build_sha256": kid,
                "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
                "traffic_bytes_per_launch": fetch_b + write_b, "dispatches": fe[kb][1],
                "copy_calibration": {"bytes": copy_bytes, "fetch_kib": cf, "write_kib": cw, "fetch_factor": ff,

@@ -24,11 +24,22 @@ FLAGS = [
     "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
     "-I", os.path.join(ROOT, "include"),
 ]
+# per-source additions: the kernels take the machine scheduler that groups memory
+# instructions into clauses (measured about 1 % faster on the wave kernel)
+SOURCE_FLAGS = {"dic_kernels.hip": ["-mllvm", "-amdgpu-sched-strategy=max-memory-clause"]}
+
+
+def kernel_build_id() -> str:
+    """sha256 of the wave kernels' source and the flags they are compiled with."""
+    import hashlib
+    h = hashlib.sha256(open(os.path.join(CSRC, "dic_kernels.hip"), "rb").read())
+    h.update(repr(FLAGS + SOURCE_FLAGS["dic_kernels.hip"]).encode())
+    return h.hexdigest()
 
 
 def _compile(src: str, build_dir: str) -> str:
     obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *SOURCE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, r.stdout, r.stderr))
