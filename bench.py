@@ -38,32 +38,89 @@ PEAK_HBM_GBPS = 8000.0                   # MI355X published HBM3E bandwidth
 def render_frames(w, nframes):
     """Reference plus `nframes` deformed frames that differ only in their noise."""
     from paper_2601_12941_amd import synth
-    X, Y, S, A = synth.draw_blobs(w.W, w.H, w.nblobs, w.sigma, w.amp, w.seed_blobs)
-    ref_clean = synth._render_blobs(w.W, w.H, X, Y, S, A)
-    f = w.field()
-    u, v = f(X, Y)
-    def_clean = synth._render_blobs(w.W, w.H, X + u, Y + v, S, A)
-    ref = synth._finish(ref_clean, w.noise, w.seed_noise_ref, w.bits)
-    frames = [synth._finish(def_clean, w.noise, w.seed_noise_def + i, w.bits) for i in range(nframes)]
-    roi = synth.roi_from_field(w.W, w.H, f)
-    return ref, frames, roi
+    return synth.noise_frames(w, nframes)
 
 
-def cpu_baseline(ref, deformed, roi, w, crop):
-    """The FP64 oracle on the central crop x crop window of the same pair."""
+def host_info():
+    """The host CPUs the oracle baseline runs on (nproc, lscpu's model and topology)."""
+    import subprocess
+    info = {"os_cpu_count": os.cpu_count()}
+    try:
+        info["affinity"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    try:
+        info["nproc"] = int(subprocess.run(["nproc"], capture_output=True, text=True, timeout=10).stdout.strip())
+    except Exception:
+        pass
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        keep = ("Model name", "CPU(s)", "Thread(s) per core", "Core(s) per socket", "Socket(s)", "CPU max MHz")
+        info["lscpu"] = {k.strip(): v.strip() for k, v in (ln.split(":", 1) for ln in out.splitlines() if ":" in ln)
+                         if k.strip() in keep}
+    except Exception:
+        pass
+    return info
+
+
+def _oracle_crop(ref, deformed, roi, w, crop, threads):
     import oracle
     H, W = ref.shape
     y0, x0 = (H - crop) // 2, (W - crop) // 2
     sl = (slice(y0, y0 + crop), slice(x0, x0 + crop))
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(16, os.cpu_count() or 1)
-    prm = w.params()
     t0 = time.perf_counter()
-    r = oracle.correlate(ref[sl], deformed[sl], roi[sl], seeds=[(crop / 2, crop / 2, 0, 0)], threads=threads, **prm)
-    dt = time.perf_counter() - t0
+    r = oracle.correlate(ref[sl], deformed[sl], roi[sl], seeds=[(crop / 2, crop / 2, 0, 0)], threads=threads,
+                         **w.params())
+    return r, time.perf_counter() - t0
+
+
+def cpu_baseline(ref, deformed, roi, w, crop, single_crop):
+    """The FP64 oracle (WAVE order, OpenMP over the nodes of each wave) on the
+    central crop x crop window of the same pair with the host's CPU share, and on
+    the central single_crop window on one core.  Returns the record and the
+    multi-core oracle result (the whole pair when crop is the image side)."""
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(16, os.cpu_count() or 1)
+    r, dt = _oracle_crop(ref, deformed, roi, w, crop, threads)
     conv = int((r["status"] == 0).sum())
-    return {"value": conv / dt, "unit": "converged subsets/s", "cores": threads, "kind": "oracle",
-            "sample": "central %dx%d window of the same pair (%d converged subsets in %.1f s, WAVE order, "
-                      "OpenMP over the nodes of each wave)" % (crop, crop, conv, dt)}
+    rec = {"value": conv / dt, "unit": "converged subsets/s", "cores": threads, "kind": "oracle",
+           "sample": "central %dx%d window of the same pair (%d converged subsets in %.1f s, WAVE order, "
+                     "OpenMP over the nodes of each wave, %d threads)" % (crop, crop, conv, dt, threads),
+           "host": host_info()}
+    if single_crop > 0:
+        r1, dt1 = _oracle_crop(ref, deformed, roi, w, single_crop, 1)
+        c1 = int((r1["status"] == 0).sum())
+        rec["single_core"] = {"value": c1 / dt1, "unit": "converged subsets/s", "cores": 1,
+                              "sample": "central %dx%d window (%d converged subsets in %.1f s)" % (
+                                  single_crop, single_crop, c1, dt1)}
+    return rec, r
+
+
+def accuracy(g, o, w, truth=None):
+    """Error of a GPU result against the FP64 oracle on the same pair (nodes both
+    call CONVERGED), status and wave-index agreement, and error against the
+    ground-truth field at the node centres."""
+    gs, os_ = g["status"].astype(np.int32), o["status"]
+    active = os_ != 2
+    both = (gs == 0) & (os_ == 0)
+    du = np.abs(g["p"][0].astype(np.float64) - o["p"][0])[both]
+    dv = np.abs(g["p"][1].astype(np.float64) - o["p"][1])[both]
+    dz = np.abs(g["zncc"].astype(np.float64) - o["zncc"])[both]
+    h = (w.N - 1) / 2.0
+    dgrad = np.abs(g["p"][2:6].astype(np.float64) - o["p"][2:6])[:, both] * h
+    rep = {"nodes_compared": int(both.sum()), "max_du_px": float(du.max()), "max_dv_px": float(dv.max()),
+           "rms_du_px": float(np.sqrt(np.mean(du ** 2))), "rms_dv_px": float(np.sqrt(np.mean(dv ** 2))),
+           "p999_duv_px": float(np.percentile(np.maximum(du, dv), 99.9)),
+           "max_dgrad_times_h_px": float(dgrad.max()), "max_dzncc": float(dz.max()),
+           "status_mismatch": float((gs != os_)[active].mean()),
+           "wave_mismatch": float((g["wave"] != o["wave"])[both].mean())}
+    if truth is not None:
+        u, v = truth
+        conv = gs == 0
+        eu = np.abs(g["p"][0].astype(np.float64) - u)[conv]
+        ev = np.abs(g["p"][1].astype(np.float64) - v)[conv]
+        rep["vs_truth"] = {"rms_du_px": float(np.sqrt(np.mean(eu ** 2))), "rms_dv_px": float(np.sqrt(np.mean(ev ** 2))),
+                           "max_du_px": float(eu.max()), "max_dv_px": float(ev.max())}
+    return rep
 
 
 def profiled_traffic():
@@ -582,7 +639,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=16, help="deformed frames per batched step")
-    ap.add_argument("--latency-runs", type=int, default=30, help="plain single-frame calls for p50/p99")
+    ap.add_argument("--latency-runs", type=int, default=60, help="plain single-frame calls for p50/p99")
     ap.add_argument("--size", type=int, default=2048)
     ap.add_argument("--fp32-reductions", action="store_true")
     ap.add_argument("--tps", type=int, default=0, help="threads per subset, batched form (0: autotuned)")
@@ -591,7 +648,12 @@ def main():
     ap.add_argument("--plain-tile", type=int, default=0, help="LDS window side, plain form")
     ap.add_argument("--tune-size", type=int, default=0,
                     help="side of the autotuner's pair (0: the benchmark's own pair)")
-    ap.add_argument("--cpu-crop", type=int, default=2048, help="oracle sample window (0 = skip)")
+    ap.add_argument("--cpu-crop", type=int, default=2048,
+                    help="oracle window on the host's CPU share (0 = skip; the image side = the whole pair, which "
+                         "also gives the accuracy fields)")
+    ap.add_argument("--single-crop", type=int, default=512, help="oracle window on one core (0 = skip)")
+    ap.add_argument("--no-fp32-variant", action="store_true",
+                    help="skip timing the FP32-reduction variant beside the FP64-reduction default")
     ap.add_argument("--workload", default="2048", choices=["2048", "gigapixel", "serve", "precision"],
                     help="2048: the 2048^2 batched/plain benchmark; gigapixel: the 32768^2 pair, repeated; "
                          "serve: the serving mix")
@@ -696,7 +758,7 @@ def main():
     launches = 0
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        eng.correlate_batch(d_frames, seeds)
+        bout = eng.correlate_batch(d_frames, seeds)
         st = eng.stats()
         conv += st["converged"]
         iters += st["iterations"]
@@ -706,21 +768,55 @@ def main():
     t_batch = time.perf_counter() - t0
     last = eng.stats()
     value = conv / t_batch
+    batched_frame0 = {k: v.cpu().numpy() for k, v in bout[0].items()}
+    del bout
 
     # ---- plain single-frame calls: throughput and pair latency
-    peng.correlate(d_frames[0], seeds)
-    torch.cuda.synchronize()
-    lat = []
-    pconv = 0
-    for i in range(args.latency_runs):
+    def plain_runs(engine, runs):
+        engine.correlate(d_frames[0], seeds)
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        peng.correlate(d_frames[i % len(d_frames)], seeds)
+        lat, pc, first = [], 0, None
+        for i in range(runs):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            out = engine.correlate(d_frames[i % len(d_frames)], seeds)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t1)
+            pc += engine.stats()["converged"]
+            if i == 0:
+                first = {k: v.cpu().numpy() for k, v in out.items()}
+        return pc / sum(lat), np.array(lat) * 1e3, first
+    plain_rate, lat_ms, plain_frame0 = plain_runs(peng, args.latency_runs)
+
+    # ---- the FP32-reduction variant of both forms, same launch shapes
+    fp32 = None
+    if not args.no_fp32_variant and not args.fp32_reductions:
+        veng = dic.Engine(0)
+        veng.set_reference(d_ref, d_roi, **{**prm, "reduce_fp64": False})
+        vpeng = dic.Engine(0)
+        vpeng.set_reference(d_ref, d_roi, **{**prm, "reduce_fp64": False, "threads_per_subset": tps_p,
+                                              "tile_side": tile_p})
+        veng.correlate_batch(d_frames, seeds)
         torch.cuda.synchronize()
-        lat.append(time.perf_counter() - t1)
-        pconv += peng.stats()["converged"]
-    plain_rate = pconv / sum(lat)
-    lat_ms = np.array(lat) * 1e3
+        vsteps = max(1, min(args.steps, 5))
+        vconv = 0
+        t0 = time.perf_counter()
+        for _ in range(vsteps):
+            vout = veng.correlate_batch(d_frames, seeds)
+            vconv += veng.stats()["converged"]
+        torch.cuda.synchronize()
+        vt = time.perf_counter() - t0
+        v_frame0 = {k: v.cpu().numpy() for k, v in vout[0].items()}
+        del vout
+        vrate, vlat, vplain0 = plain_runs(vpeng, max(20, args.latency_runs // 3))
+        fp32 = {"batched": {"value": vconv / vt, "unit": "converged subsets/s", "steps": vsteps,
+                            "ms_per_step": vt / vsteps * 1e3},
+                "plain": {"value": vrate, "unit": "converged subsets/s",
+                          "latency_ms_p50": float(np.percentile(vlat, 50)),
+                          "latency_ms_p99": float(np.percentile(vlat, 99)), "runs": len(vlat)},
+                "_frames": (v_frame0, vplain0)}
+        veng.close()
+        vpeng.close()
 
     # ---- roofline of the IC-GN wave kernel (plain FP32 VALU arithmetic)
     N = w.N
@@ -729,22 +825,41 @@ def main():
     achieved = flops / (kern_ms * 1e-3) / 1e12
     # the committed counters describe the profiled launch shape only
     profiled = (args.batch == 16 and args.size == 2048 and last["threads_per_subset"] == PROFILE_SHAPES["tps"]
-                and tile_b == PROFILE_SHAPES["tile"])
+                and tile_b == PROFILE_SHAPES["tile"] and not args.fp32_reductions)
     traffic = profiled_traffic() if profiled else None
     roofline = {"bound": "alu", "kernel": "k_wave (IC-GN frontier wave)", "achieved": achieved,
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                 "traffic": traffic,
                 "flop_per_px_iter": FLOP_PER_PX_IT[w.shape], "avg_launch_us": avg_launch_ms * 1e3,
-                "launches_per_step": launches / args.steps}
+                "launches_per_step": launches / args.steps,
+                "subsets_per_launch": conv / max(1, launches)}
     if traffic:
-        # the same launch against the HBM roof: counted bytes over the live launch time
+        # the same launch against the HBM roof: counted bytes over the live launch time,
+        # and the counted bytes over the compulsory ones (each frame's deformed image and
+        # coefficients once, the reference arrays once per launch)
         gbps = traffic / (avg_launch_ms * 1e-3) / 1e9
         roofline["traffic_gbps"] = gbps
         roofline["traffic_frac_of_hbm"] = gbps / PEAK_HBM_GBPS
+        roofline["traffic_bytes_per_subset"] = traffic / max(1.0, conv / max(1, launches))
 
     cpu = None
+    acc = None
     if args.cpu_crop > 0:
-        cpu = cpu_baseline(ref, frames[0], roi, w, min(args.cpu_crop, args.size))
+        cpu, o = cpu_baseline(ref, frames[0], roi, w, min(args.cpu_crop, args.size), args.single_crop)
+        if min(args.cpu_crop, args.size) == args.size:
+            from paper_2601_12941_amd import synth
+            u, v, _ = synth.truth_at_nodes(w.field(), w.W, w.H, w.N, w.step)
+            acc = {"batched_frame0": accuracy(batched_frame0, o, w, (u, v)),
+                   "plain_frame0": accuracy(plain_frame0, o, w, (u, v)),
+                   "oracle_vs_truth": accuracy(
+                       {"p": o["p"], "zncc": o["zncc"], "status": o["status"], "wave": o["wave"]}, o, w,
+                       (u, v))["vs_truth"]}
+            if fp32 is not None:
+                fb, fpl = fp32["_frames"]
+                fp32["accuracy"] = {"batched_frame0": accuracy(fb, o, w, (u, v)),
+                                    "plain_frame0": accuracy(fpl, o, w, (u, v))}
+    if fp32 is not None:
+        fp32.pop("_frames")
 
     rec = {
         "metric": "converged subsets/s at 2048^2 (batched vs plain, same GPU); p50/p99 pair latency",
@@ -774,6 +889,8 @@ def main():
         "set_reference_ms": t_ref * 1e3,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "accuracy_vs_oracle": acc,
+        "fp32_reductions": fp32,
         "autotune": {k: {"threads_per_subset": v["threads_per_subset"], "tile_side": v["tile_side"],
                          "proxy": v["proxy"],
                          "candidates": [[r["threads_per_subset"], r["tile_side"], round(r["rate"] / 1e6, 2)]

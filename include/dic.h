@@ -181,6 +181,49 @@ dic_status dic_destroy(dic_ctx *c);
 const char *dic_last_error(const dic_ctx *c);
 
 /* ------------------------------------------------------------------------
+ * Strain post-processing (Sec. 2.3, Eq. (6)-(9)).
+ *
+ * For every node whose window of window x window nodes (centred on it) lies
+ * inside the grid and holds only valid displacements (status CONVERGED when a
+ * status array is given, finite u and v), u_x and u_y are fitted by linear
+ * least squares in the chosen polynomial basis of the local node offsets in
+ * pixels (Eq. (8)-(9)); F = I + grad u is taken from the fit's derivatives at
+ * the window centre (Eq. (6)), and the chosen strain measure from F.  Every
+ * other node gets NaN in every output.  Bases: bilinear [1, x, y, xy] and
+ * biquadratic [1, x, y, xy, x^2, y^2, x^2 y, x y^2, x^2 y^2] (the value of the
+ * enum is the number of basis terms, the "window elements").
+ * ------------------------------------------------------------------------ */
+typedef enum { DIC_STRAIN_BILINEAR = 4, DIC_STRAIN_BIQUADRATIC = 9 } dic_strain_basis;
+
+typedef enum {
+    DIC_STRAIN_GREEN_LAGRANGE = 0, /* (F^T F - I) / 2 */
+    DIC_STRAIN_HENCKY = 1,         /* ln sqrt(F^T F) */
+    DIC_STRAIN_EULER_ALMANSI = 2,  /* (I - (F F^T)^-1) / 2 */
+    DIC_STRAIN_BIOT_RIGHT = 3,     /* sqrt(F^T F) - I */
+    DIC_STRAIN_BIOT_LEFT = 4       /* sqrt(F F^T) - I */
+} dic_strain_measure;
+
+typedef struct {
+    int32_t window;   /* nodes per side of the smoothing window: odd, 3..15 */
+    int32_t basis;    /* dic_strain_basis */
+    int32_t measure;  /* dic_strain_measure */
+} dic_strain_params;
+
+/*
+ * u, v: DEVICE float [ny][nx] displacements on a grid of `step` pixels (the
+ * u = p0 and v = p1 planes of a dic_result); status: DEVICE int8 [ny][nx] or
+ * NULL.  Outputs (caller-allocated DEVICE float): F_out [4][ny][nx] holding
+ * F_xx, F_xy, F_yx, F_yy and eps_out [3][ny][nx] holding eps_xx, eps_xy,
+ * eps_yy.  Ordered on the context's stream (no reference needed); returns
+ * after completion.  DIC_E_INVAL for a bad window, basis, measure or size.
+ */
+dic_status dic_strain(dic_ctx *c, const float *u, const float *v, const int8_t *status, int32_t nx, int32_t ny,
+                      int32_t step, const dic_strain_params *prm, float *F_out, float *eps_out);
+
+/* Virtual strain gauge of Eq. (7) in pixels: (window - 1) * step + subset_size. */
+int32_t dic_vsg(int32_t window, int32_t step, int32_t subset_size);
+
+/* ------------------------------------------------------------------------
  * Serving: continuous batching of correlation requests.
  *
  * A server keeps reference precomputes resident (dic_server_add_reference,

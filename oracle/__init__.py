@@ -181,4 +181,4 @@ def correlate(ref, deformed, roi=None, *, subset_size, step, shape=6, tol=1e-4, 
     if ns < 0:
         raise ValueError("no seed could be placed on an active node")
     return dict(p=p, zncc=z, iters=it, status=st, wave=wv, seed_nodes=so[:ns], nx=nx, ny=ny, seconds=dt,
-                u=p[0], v=p[1])
+                u=p[0], v=p[1], subset_size=N, step=step)

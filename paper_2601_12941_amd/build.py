@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdicmi.so")
-SOURCES = ["dic_kernels.hip", "dic_engine.hip", "dic_server.hip"]
+SOURCES = ["dic_kernels.hip", "dic_engine.hip", "dic_server.hip", "dic_strain.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("DIC_OFFLOAD_ARCH", "gfx950")
 
@@ -29,11 +29,23 @@ FLAGS = [
 SOURCE_FLAGS = {"dic_kernels.hip": ["-mllvm", "-amdgpu-sched-strategy=max-memory-clause"]}
 
 
-def kernel_build_id() -> str:
-    """sha256 of the wave kernels' source and the flags they are compiled with."""
+# files whose text decides the wave kernels' code: the kernel source and the
+# headers it includes (paths relative to the repository root)
+KERNEL_INPUTS = ["paper_2601_12941_amd/csrc/dic_kernels.hip", "paper_2601_12941_amd/csrc/dic_internal.h",
+                 "paper_2601_12941_amd/csrc/dic_device.h"]
+
+
+def kernel_build_id(root: str = ROOT) -> str:
+    """sha256 of the wave kernels' source, the headers it includes and the flags
+    they are compiled with.  Absolute paths in the flags are written relative to
+    the checkout, so the id is the same wherever the repository sits."""
     import hashlib
-    h = hashlib.sha256(open(os.path.join(CSRC, "dic_kernels.hip"), "rb").read())
-    h.update(repr(FLAGS + SOURCE_FLAGS["dic_kernels.hip"]).encode())
+    h = hashlib.sha256()
+    for rel in KERNEL_INPUTS:
+        h.update(rel.encode())
+        h.update(open(os.path.join(root, rel), "rb").read())
+    flags = [f.replace(ROOT, "<root>") for f in FLAGS + SOURCE_FLAGS["dic_kernels.hip"]]
+    h.update(repr(flags).encode())
     return h.hexdigest()
 
 

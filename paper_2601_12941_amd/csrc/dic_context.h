@@ -20,12 +20,32 @@ struct FrameBuf {
     int32_t *list0 = nullptr, *list1 = nullptr, *counts = nullptr;
     double *seed_p = nullptr;
     int32_t *seed_nodes = nullptr;
+    int seed_capacity = 0;       // seeds seed_p / seed_nodes hold
     unsigned long long *stat = nullptr;
 };
 
 inline size_t pixel_size(int pixel) { return pixel == DIC_PIX_U8 ? 1 : (pixel == DIC_PIX_U16 ? 2 : 4); }
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+// Shared steps of the correlate entry points (dic_engine.hip).
+dic_status check_correlate_args(dic_ctx *c, const dic_image *defs, int32_t nframes, const dic_seed *seeds,
+                                int32_t nseeds, const dic_result *outs);
+// Seeds of every frame snapped to active nodes and de-duplicated, with the
+// centres of their integer searches; host arrays of nframes*nseeds and
+// 2*nframes*nseeds entries, nuniq[nframes].
+dic_status snap_frame_seeds(dic_ctx *c, const dic_seed *seeds, int nframes, int nseeds, int32_t *seed_nodes,
+                            int32_t *centre, int *nuniq);
+// Host record of one frame over device buffers the caller provides.
+void fill_frame(const dic_ctx *c, FrameState &F, const dic_image &def, const dic_result &out, void *dcoef_base,
+                uint64_t *pkey, int32_t *list0, int32_t *list1, int32_t *counts, double *seed_p,
+                int32_t *seed_nodes, int nseeds, unsigned long long *stat);
+// Prefilter, seed search, every wave, finalisation and counters of nframes
+// frames whose records hf[] point at allocated buffers; allocates nothing
+// (chunk_timing: per-chunk events, created on first use).
+dic_status run_frames(dic_ctx *c, const dic_image *defs, int nframes, int nseeds, const FrameState *hf,
+                      FrameState *d_frames, const int32_t *h_seed_nodes, const int32_t *h_centre, int32_t *d_centre,
+                      double *d_zbuf, bool chunk_timing);
 
 } // namespace dicmi
 
@@ -62,6 +82,8 @@ struct dic_ctx {
     int32_t *d_wave_total = nullptr;
     RefView *d_view = nullptr;   // device copy of view(), read by the wave kernel
     int32_t *h_pinned = nullptr;
+    unsigned long long *h_stats = nullptr;  // pinned: 4 counters per frame, then the last frame's seed shift
+    double *d_strain_w = nullptr;           // least-squares derivative weights of dic_strain
     hipEvent_t ev[4] = {};
     std::vector<hipEvent_t> chunk_ev;
     dic_stats stats{};

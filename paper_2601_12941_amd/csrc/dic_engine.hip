@@ -33,7 +33,11 @@ dic_status dic_create(dic_ctx **out, int device, void *hip_stream)
             delete c;
             return DIC_E_DEVICE;
         }
-    if (hipHostMalloc(reinterpret_cast<void **>(&c->h_pinned), 64 * sizeof(int32_t)) != hipSuccess) {
+    if (hipHostMalloc(reinterpret_cast<void **>(&c->h_pinned), 64 * sizeof(int32_t)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&c->h_stats), sizeof(unsigned long long) * (4 * kMaxFrames + 2)) !=
+            hipSuccess) {
+        if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+        if (c->h_stats) (void)hipHostFree(c->h_stats);
         delete c;
         return DIC_E_DEVICE;
     }
@@ -53,7 +57,9 @@ dic_status dic_destroy(dic_ctx *c)
     dfree(c->d_frames);
     dfree(c->d_centre);
     dfree(c->d_zbuf);
+    dfree(c->d_strain_w);
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+    if (c->h_stats) (void)hipHostFree(c->h_stats);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto &e : c->chunk_ev) (void)hipEventDestroy(e);
@@ -150,7 +156,12 @@ dic_status dic_set_reference(dic_ctx *c, const dic_image *ref, const uint8_t *ro
                      c->cpitch, false, s);
     launch_ref_pixels(R, c->pf, c->pfx, c->pfy, s);
     launch_active(roi_mask_dev, R, c->flag, s);
-    launch_ref_nodes(R, c->np, tps, c->cache, c->flag, s);
+    if (!launch_ref_nodes(R, c->np, tps, c->cache, c->flag, s)) {
+        HIPCHK(hipStreamSynchronize(s));
+        free_reference(c);
+        FAIL(DIC_E_UNSUPPORTED, "no reference-precompute kernel for shape %d, %d threads, subset %d", c->np, tps,
+             p.subset_size);
+    }
     HIPCHK(hipGetLastError());
     c->flag_host.resize(c->nodes);
     HIPCHK(hipMemcpyAsync(c->flag_host.data(), c->flag, c->nodes, hipMemcpyDeviceToHost, s));
@@ -165,11 +176,13 @@ dic_status dic_set_reference(dic_ctx *c, const dic_image *ref, const uint8_t *ro
     return DIC_OK;
 }
 
-dic_status dic_correlate_batch(dic_ctx *c, const dic_image *defs, int32_t nframes, const dic_seed *seeds,
-                               int32_t nseeds, dic_result *outs)
+} // extern "C"
+
+namespace dicmi {
+
+dic_status check_correlate_args(dic_ctx *c, const dic_image *defs, int32_t nframes, const dic_seed *seeds,
+                                int32_t nseeds, const dic_result *outs)
 {
-    if (!c) return DIC_E_INVAL;
-    c->err.clear();
     if (!c->has_ref) FAIL(DIC_E_STATE, "dic_correlate before dic_set_reference");
     if (nframes < 1 || nframes > kMaxFrames) FAIL(DIC_E_INVAL, "nframes %d (1..%d)", nframes, kMaxFrames);
     if (!defs || !outs) FAIL(DIC_E_INVAL, "NULL images or results");
@@ -187,16 +200,14 @@ dic_status dic_correlate_batch(dic_ctx *c, const dic_image *defs, int32_t nframe
         if (!std::isfinite(seeds[q].x) || !std::isfinite(seeds[q].y) || !std::isfinite(seeds[q].u0) ||
             !std::isfinite(seeds[q].v0))
             FAIL(DIC_E_INVAL, "seed %d is not finite", q);
+    return DIC_OK;
+}
 
-    HIPCHK(hipSetDevice(c->device));
-    hipStream_t s = c->stream;
-    dic_status st = ensure_frames(c, nframes);
-    if (st != DIC_OK) return st;
-
-    // seeds: snap to active nodes, de-duplicate per frame, integer search centre
-    std::vector<int32_t> seed_nodes(static_cast<size_t>(nframes) * nseeds), centre(2 * nframes * nseeds);
-    std::vector<int> nuniq(nframes, 0);
+dic_status snap_frame_seeds(dic_ctx *c, const dic_seed *seeds, int nframes, int nseeds, int32_t *seed_nodes,
+                            int32_t *centre, int *nuniq)
+{
     for (int f = 0; f < nframes; ++f) {
+        nuniq[f] = 0;
         for (int q = 0; q < nseeds; ++q) {
             const dic_seed &sd = seeds[f * nseeds + q];
             const int64_t node = snap_seed(c, sd.x, sd.y);
@@ -211,6 +222,163 @@ dic_status dic_correlate_batch(dic_ctx *c, const dic_image *defs, int32_t nframe
         }
         if (nuniq[f] == 0) FAIL(DIC_E_NOSEED, "frame %d: no seed lies on an active node", f);
     }
+    return DIC_OK;
+}
+
+void fill_frame(const dic_ctx *c, FrameState &F, const dic_image &def, const dic_result &out, void *dcoef_base,
+                uint64_t *pkey, int32_t *list0, int32_t *list1, int32_t *counts, double *seed_p,
+                int32_t *seed_nodes, int nseeds, unsigned long long *stat)
+{
+    const size_t esz = c->prm.coef_fp16 ? sizeof(__half) : sizeof(float);
+    F.dcoef = static_cast<char *>(dcoef_base) + (kPad * c->cpitch + kPad) * esz;
+    F.dpitch = c->cpitch;
+    F.draw = def.data;
+    F.draw_pitch = def.pitch_bytes;
+    F.dpixel = def.pixel;
+    F.p = out.p;
+    F.zncc = out.zncc;
+    F.iters = out.iters;
+    F.status = out.status;
+    F.wave = out.wave;
+    F.pkey = pkey;
+    F.list0 = list0;
+    F.list1 = list1;
+    F.counts = counts;
+    F.seed_p = seed_p;
+    F.seed_nodes = seed_nodes;
+    F.nseeds = nseeds;
+    F.stat = stat;
+    F.ref = c->d_view;
+    F.k_base = 0;
+    F.kmax = static_cast<int>(c->nodes + 1);
+}
+
+dic_status run_frames(dic_ctx *c, const dic_image *defs, int nframes, int nseeds, const FrameState *hf,
+                      FrameState *d_frames, const int32_t *h_seed_nodes, const int32_t *h_centre, int32_t *d_centre,
+                      double *d_zbuf, bool chunk_timing)
+{
+    hipStream_t s = c->stream;
+    const bool half = c->prm.coef_fp16 != 0;
+    RefView R = c->view();
+    HIPCHK(hipEventRecord(c->ev[0], s));
+    for (int f = 0; f < nframes; ++f) {
+        const FrameState &F = hf[f];
+        launch_prefilter(defs[f].data, defs[f].pitch_bytes, defs[f].pixel, c->W, c->H, c->tmp, c->tpitch,
+                         const_cast<void *>(F.dcoef), c->cpitch, half, s);
+        launch_init_frame(R, F, c->np, s);
+        launch_zero32(F.stat, 8, s);
+        HIPCHK(hipMemcpyAsync(F.seed_nodes, h_seed_nodes + f * nseeds, sizeof(int32_t) * nseeds,
+                              hipMemcpyHostToDevice, s));
+    }
+    HIPCHK(hipEventRecord(c->ev[1], s));
+    HIPCHK(hipMemcpyAsync(d_centre, h_centre, sizeof(int32_t) * 2 * nframes * nseeds, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_frames, hf, sizeof(FrameState) * nframes, hipMemcpyHostToDevice, s));
+    launch_zero32(c->d_wave_total, c->nodes + 130, s);
+    launch_seed_search(R, d_frames, nframes, nseeds, c->prm.seed_radius, d_centre, d_zbuf, s);
+    launch_seed_pick(R, d_frames, nframes, nseeds, c->prm.seed_radius, d_centre, d_zbuf, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(c->ev[2], s));
+
+    const int grid = wave_grid_hint(c->np, c->tps, c->device);
+    FrameTable table;
+    std::memset(&table, 0, sizeof(table));
+    for (int f = 0; f < nframes; ++f) table.f[f] = hf[f];
+    table.n = nframes;
+    const bool f64 = c->prm.reduce_fp64 != 0;
+    int k = 0, chunk = 4, nchunk = 0;
+    for (;;) {
+        if (chunk_timing) {
+            if (static_cast<int>(c->chunk_ev.size()) < 2 * (nchunk + 1)) {
+                hipEvent_t a, b;
+                HIPCHK(hipEventCreate(&a));
+                HIPCHK(hipEventCreate(&b));
+                c->chunk_ev.push_back(a);
+                c->chunk_ev.push_back(b);
+            }
+            HIPCHK(hipEventRecord(c->chunk_ev[2 * nchunk], s));
+        }
+        for (int j = 0; j < chunk && k <= c->nodes; ++j, ++k)
+            if (!launch_wave(table, k, c->np, c->prm.subset_size, c->tps, f64, R.ts, grid, s))
+                FAIL(DIC_E_UNSUPPORTED, "no kernel for shape %d, %d threads, subset %d", c->np, c->tps,
+                     c->prm.subset_size);
+        HIPCHK(hipGetLastError());
+        if (chunk_timing) HIPCHK(hipEventRecord(c->chunk_ev[2 * nchunk + 1], s));
+        ++nchunk;
+        // size of the next wave, summed over the frames
+        launch_count_wave(d_frames, nframes, k, c->d_wave_total, s);
+        HIPCHK(hipMemcpyAsync(c->h_pinned, c->d_wave_total + k, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (c->h_pinned[0] == 0 || k > c->nodes) break;
+        chunk = std::min(chunk * 2, 64);
+    }
+    HIPCHK(hipEventRecord(c->ev[3], s));
+    for (int f = 0; f < nframes; ++f) {
+        launch_frame_stats(R, hf[f], s);
+        launch_finalize(R, hf[f], c->np, c->prm.nan_unconverged != 0, s);
+    }
+    HIPCHK(hipGetLastError());
+
+    // counters: per frame computed / converged / iterations / waves (largest wave
+    // index + 1); the call's wave count is the longest frame's
+    unsigned long long *hs = c->h_stats;
+    for (int f = 0; f < nframes; ++f)
+        HIPCHK(hipMemcpyAsync(hs + 4 * f, hf[f].stat, sizeof(unsigned long long) * 4, hipMemcpyDeviceToHost, s));
+    double *sp = reinterpret_cast<double *>(hs + 4 * kMaxFrames);
+    HIPCHK(hipMemcpyAsync(sp, hf[nframes - 1].seed_p, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    dic_stats S{};
+    S.nodes = c->nodes;
+    S.active = c->active;
+    S.threads_per_subset = c->tps;
+    S.frames = nframes;
+    for (int f = 0; f < nframes; ++f) {
+        S.computed += static_cast<int64_t>(hs[4 * f + 0]);
+        S.converged += static_cast<int64_t>(hs[4 * f + 1]);
+        S.iterations += static_cast<int64_t>(hs[4 * f + 2]);
+        S.waves = std::max(S.waves, static_cast<int32_t>(hs[4 * f + 3]));
+    }
+    S.seed_du = static_cast<int32_t>(sp[0]);
+    S.seed_dv = static_cast<int32_t>(sp[1]);
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev[0], c->ev[3]));
+    S.ms_total = ms;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev[2], c->ev[3]));
+    S.ms_icgn = ms;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+    S.ms_prefilter = ms;
+    S.wave_launches = k;
+    if (chunk_timing) {
+        for (int q = 0; q < nchunk; ++q) {
+            HIPCHK(hipEventElapsedTime(&ms, c->chunk_ev[2 * q], c->chunk_ev[2 * q + 1]));
+            S.ms_wave_kernels += ms;
+        }
+    } else {
+        S.ms_wave_kernels = S.ms_icgn;
+    }
+    c->stats = S;
+    return DIC_OK;
+}
+
+} // namespace dicmi
+
+extern "C" {
+
+dic_status dic_correlate_batch(dic_ctx *c, const dic_image *defs, int32_t nframes, const dic_seed *seeds,
+                               int32_t nseeds, dic_result *outs)
+{
+    if (!c) return DIC_E_INVAL;
+    c->err.clear();
+    dic_status st = check_correlate_args(c, defs, nframes, seeds, nseeds, outs);
+    if (st != DIC_OK) return st;
+    HIPCHK(hipSetDevice(c->device));
+    st = ensure_frames(c, nframes);
+    if (st != DIC_OK) return st;
+
+    // seeds: snap to active nodes, de-duplicate per frame, integer search centre
+    std::vector<int32_t> seed_nodes(static_cast<size_t>(nframes) * nseeds), centre(2 * nframes * nseeds);
+    std::vector<int> nuniq(nframes, 0);
+    st = snap_frame_seeds(c, seeds, nframes, nseeds, seed_nodes.data(), centre.data(), nuniq.data());
+    if (st != DIC_OK) return st;
     const int side = 2 * c->prm.seed_radius + 1;
     const int need_z = nframes * nseeds * side * side;
     if (need_z > c->zbuf_capacity) {
@@ -223,142 +391,22 @@ dic_status dic_correlate_batch(dic_ctx *c, const dic_image *defs, int32_t nframe
         HIPCHK(hipMalloc(&c->d_centre, sizeof(int32_t) * 2 * nframes * nseeds));
         c->centre_capacity = 2 * nframes * nseeds;
     }
-    for (int f = 0; f < nframes; ++f) {
-        FrameBuf &fb = c->frames[f];
-        dfree(fb.seed_p);
-        dfree(fb.seed_nodes);
-        HIPCHK(hipMalloc(&fb.seed_p, sizeof(double) * 2 * nseeds));
-        HIPCHK(hipMalloc(&fb.seed_nodes, sizeof(int32_t) * nseeds));
-    }
-
-    const bool half = c->prm.coef_fp16 != 0;
-    RefView R = c->view();
-    HIPCHK(hipEventRecord(c->ev[0], s));
     c->h_frames.resize(nframes);
     for (int f = 0; f < nframes; ++f) {
+        // seed buffers only grow: repeated calls with the same seed count allocate nothing
         FrameBuf &fb = c->frames[f];
-        FrameState &F = c->h_frames[f];
-        const size_t esz = half ? sizeof(__half) : sizeof(float);
-        F.dcoef = static_cast<char *>(fb.dcoef_base) + (kPad * c->cpitch + kPad) * esz;
-        F.dpitch = c->cpitch;
-        F.draw = defs[f].data;
-        F.draw_pitch = defs[f].pitch_bytes;
-        F.dpixel = defs[f].pixel;
-        F.p = outs[f].p;
-        F.zncc = outs[f].zncc;
-        F.iters = outs[f].iters;
-        F.status = outs[f].status;
-        F.wave = outs[f].wave;
-        F.pkey = fb.pkey;
-        F.list0 = fb.list0;
-        F.list1 = fb.list1;
-        F.counts = fb.counts;
-        F.seed_p = fb.seed_p;
-        F.seed_nodes = fb.seed_nodes;
-        F.nseeds = nuniq[f];
-        F.stat = fb.stat;
-        F.ref = c->d_view;
-        F.k_base = 0;
-        F.kmax = static_cast<int>(c->nodes + 1);
-        launch_prefilter(defs[f].data, defs[f].pitch_bytes, defs[f].pixel, c->W, c->H, c->tmp, c->tpitch,
-                         const_cast<void *>(F.dcoef), c->cpitch, half, s);
-        launch_init_frame(R, F, c->np, s);
-        HIPCHK(hipMemsetAsync(fb.stat, 0, sizeof(unsigned long long) * 4, s));
-        HIPCHK(hipMemcpyAsync(fb.seed_nodes, seed_nodes.data() + f * nseeds, sizeof(int32_t) * nseeds,
-                              hipMemcpyHostToDevice, s));
-    }
-    HIPCHK(hipEventRecord(c->ev[1], s));
-    HIPCHK(hipMemcpyAsync(c->d_centre, centre.data(), sizeof(int32_t) * 2 * nframes * nseeds, hipMemcpyHostToDevice,
-                          s));
-    HIPCHK(hipMemcpyAsync(c->d_frames, c->h_frames.data(), sizeof(FrameState) * nframes, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemsetAsync(c->d_wave_total, 0, sizeof(int32_t) * (c->nodes + 130), s));
-    launch_seed_search(R, c->d_frames, nframes, nseeds, c->prm.seed_radius, c->d_centre, c->d_zbuf, s);
-    launch_seed_pick(R, c->d_frames, nframes, nseeds, c->prm.seed_radius, c->d_centre, c->d_zbuf, s);
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipEventRecord(c->ev[2], s));
-
-    const int grid = wave_grid_hint(c->np, c->tps, c->device);
-    FrameTable table;
-    std::memset(&table, 0, sizeof(table));
-    for (int f = 0; f < nframes; ++f) table.f[f] = c->h_frames[f];
-    table.n = nframes;
-    const bool f64 = c->prm.reduce_fp64 != 0;
-    int k = 0, chunk = 4, waves = 0, nchunk = 0;
-    for (;;) {
-        if (static_cast<int>(c->chunk_ev.size()) < 2 * (nchunk + 1)) {
-            hipEvent_t a, b;
-            HIPCHK(hipEventCreate(&a));
-            HIPCHK(hipEventCreate(&b));
-            c->chunk_ev.push_back(a);
-            c->chunk_ev.push_back(b);
+        if (nseeds > fb.seed_capacity) {
+            dfree(fb.seed_p);
+            dfree(fb.seed_nodes);
+            HIPCHK(hipMalloc(&fb.seed_p, sizeof(double) * 2 * nseeds));
+            HIPCHK(hipMalloc(&fb.seed_nodes, sizeof(int32_t) * nseeds));
+            fb.seed_capacity = nseeds;
         }
-        HIPCHK(hipEventRecord(c->chunk_ev[2 * nchunk], s));
-        for (int j = 0; j < chunk && k <= c->nodes; ++j, ++k)
-            if (!launch_wave(table, k, c->np, c->prm.subset_size, c->tps, f64, R.ts, grid, s))
-                FAIL(DIC_E_UNSUPPORTED, "no kernel for shape %d, %d threads, subset %d", c->np, c->tps,
-                     c->prm.subset_size);
-        HIPCHK(hipGetLastError());
-        HIPCHK(hipEventRecord(c->chunk_ev[2 * nchunk + 1], s));
-        ++nchunk;
-        // size of the next wave, summed over the frames
-        launch_count_wave(c->d_frames, nframes, k, c->d_wave_total, s);
-        HIPCHK(hipMemcpyAsync(c->h_pinned, c->d_wave_total + k, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        if (c->h_pinned[0] == 0 || k > c->nodes) break;
-        chunk = std::min(chunk * 2, 64);
+        fill_frame(c, c->h_frames[f], defs[f], outs[f], fb.dcoef_base, fb.pkey, fb.list0, fb.list1, fb.counts,
+                   fb.seed_p, fb.seed_nodes, nuniq[f], fb.stat);
     }
-    HIPCHK(hipEventRecord(c->ev[3], s));
-    for (int f = 0; f < nframes; ++f) {
-        launch_frame_stats(R, c->h_frames[f], s);
-        launch_finalize(R, c->h_frames[f], c->np, c->prm.nan_unconverged != 0, s);
-    }
-    HIPCHK(hipGetLastError());
-
-    // counters: number of waves = first empty wave index (frame 0's counts suffice
-    // per frame; over frames, the waves of the longest frame)
-    std::vector<int32_t> wt(k + 1, 0);
-    for (int f = 0; f < nframes; ++f) {
-        std::vector<int32_t> cf(k + 1);
-        HIPCHK(hipMemcpyAsync(cf.data(), c->frames[f].counts, sizeof(int32_t) * (k + 1), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        for (int q = 0; q <= k; ++q) wt[q] += cf[q];
-    }
-    std::vector<unsigned long long> stat(4 * nframes);
-    for (int f = 0; f < nframes; ++f)
-        HIPCHK(hipMemcpyAsync(stat.data() + 4 * f, c->frames[f].stat, sizeof(unsigned long long) * 4,
-                              hipMemcpyDeviceToHost, s));
-    double sp[2] = {0, 0};
-    HIPCHK(hipMemcpyAsync(sp, c->frames[nframes - 1].seed_p, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    waves = 0;
-    while (waves <= k && wt[waves] > 0) ++waves;
-    dic_stats S{};
-    S.nodes = c->nodes;
-    S.active = c->active;
-    S.threads_per_subset = c->tps;
-    S.frames = nframes;
-    S.waves = waves;
-    for (int f = 0; f < nframes; ++f) {
-        S.computed += static_cast<int64_t>(stat[4 * f + 0]);
-        S.converged += static_cast<int64_t>(stat[4 * f + 1]);
-        S.iterations += static_cast<int64_t>(stat[4 * f + 2]);
-    }
-    S.seed_du = static_cast<int32_t>(sp[0]);
-    S.seed_dv = static_cast<int32_t>(sp[1]);
-    float ms = 0.0f;
-    HIPCHK(hipEventElapsedTime(&ms, c->ev[0], c->ev[3]));
-    S.ms_total = ms;
-    HIPCHK(hipEventElapsedTime(&ms, c->ev[2], c->ev[3]));
-    S.ms_icgn = ms;
-    HIPCHK(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
-    S.ms_prefilter = ms;
-    S.wave_launches = k;
-    for (int q = 0; q < nchunk; ++q) {
-        HIPCHK(hipEventElapsedTime(&ms, c->chunk_ev[2 * q], c->chunk_ev[2 * q + 1]));
-        S.ms_wave_kernels += ms;
-    }
-    c->stats = S;
-    return DIC_OK;
+    return run_frames(c, defs, nframes, nseeds, c->h_frames.data(), c->d_frames, seed_nodes.data(), centre.data(),
+                      c->d_centre, c->d_zbuf, true);
 }
 
 dic_status dic_correlate(dic_ctx *c, const dic_image *def, const dic_seed *seeds, int32_t nseeds, dic_result *out)

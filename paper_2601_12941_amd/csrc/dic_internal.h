@@ -95,7 +95,7 @@ void launch_prefilter(const void *src, int64_t src_pitch_bytes, int pixel, int W
                       int64_t tmp_pitch, void *dst_at_origin, int64_t dst_pitch, bool half, hipStream_t s);
 void launch_ref_pixels(const RefView &R, float *pf, float *pfx, float *pfy, hipStream_t s);
 void launch_active(const uint8_t *roi, const RefView &R, int8_t *flag, hipStream_t s);
-void launch_ref_nodes(const RefView &R, int np, int tps, double *cache, int8_t *flag, hipStream_t s);
+bool launch_ref_nodes(const RefView &R, int np, int tps, double *cache, int8_t *flag, hipStream_t s);
 void launch_init_frame(const RefView &R, const FrameState &F, int np, hipStream_t s);
 void launch_seed_search(const RefView &R, const FrameState *F_dev, int nframes, int nseeds, int radius,
                         const int32_t *seed_center_dev, double *zbuf, hipStream_t s);
@@ -106,6 +106,7 @@ bool launch_wave(const FrameTable &F, int step, int np, int N, int tps, bool f64
 void launch_gather_next(const FrameState *F_dev, int n, int step, int32_t *out, hipStream_t s);
 void launch_frame_stats(const RefView &R, const FrameState &F, hipStream_t s);
 void launch_count_wave(const FrameState *F_dev, int nframes, int k, int32_t *out, hipStream_t s);
+void launch_zero32(void *p, int64_t words, hipStream_t s);
 int pixels_per_thread(int N, int T);
 void launch_finalize(const RefView &R, const FrameState &F, int np, bool nan_unconverged, hipStream_t s);
 int wave_grid_hint(int np, int tps, int device);

@@ -12,7 +12,7 @@
 // of the subset in row-major order, their reference value and gradient in
 // registers.  The deformed coefficients around the warped subset are staged
 // in LDS and re-staged only when the warp drifts out of the staged window.
-#include "dic_internal.h"
+#include "dic_device.h"
 
 #include <algorithm>
 #include <climits>
@@ -25,139 +25,6 @@
 #pragma clang fp contract(off)
 
 namespace dicmi {
-
-// ---------------------------------------------------------------------------
-// small helpers
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ float load_pixel(const void *base, int64_t pitch_bytes, int pixel, int x, int y)
-{
-    const char *row = static_cast<const char *>(base) + static_cast<int64_t>(y) * pitch_bytes;
-    if (pixel == 0) return static_cast<float>(reinterpret_cast<const uint8_t *>(row)[x]);
-    if (pixel == 1) return static_cast<float>(reinterpret_cast<const uint16_t *>(row)[x]);
-    return reinterpret_cast<const float *>(row)[x];
-}
-
-// whole-sample mirror fold of k onto [0, n)
-__device__ __forceinline__ int fold(int k, int n)
-{
-    if (n == 1) return 0;
-    const int P = 2 * n - 2;
-    k %= P;
-    if (k < 0) k += P;
-    return k < n ? k : P - k;
-}
-
-// Cubic B-spline weights of taps x0-1 .. x0+2 at fraction t (beta3 sampled at
-// t+1, t, t-1, t-2), scaled by 6: (1-t)^3, 4 - 6t^2 + 3t^3, the same polynomial
-// at 1-t, and t^3.  The prefilter folds the 1/6 of each axis into the
-// coefficients, so the tensor product of the scaled weights with them is the
-// interpolant itself; the scaling saves the divisions by 6 and lets the mirror
-// symmetry w2(t) = w1(1-t) share the second cubic's form.
-__device__ __forceinline__ void bspline_w(float t, float &w0, float &w1, float &w2, float &w3)
-{
-    const float s = 1.0f - t;
-    const float t2 = t * t;
-    const float s2 = s * s;
-    w0 = s2 * s;
-    w1 = fmaf(fmaf(3.0f, t, -6.0f), t2, 4.0f);
-    w2 = fmaf(fmaf(3.0f, s, -6.0f), s2, 4.0f);
-    w3 = t2 * t;
-}
-
-// their derivatives with respect to t, scaled by 6 like the weights
-__device__ __forceinline__ void bspline_dw(float t, float &d0, float &d1, float &d2, float &d3)
-{
-    const float s = 1.0f - t;
-    const float t2 = t * t;
-    d0 = -3.0f * (s * s);
-    d1 = fmaf(9.0f, t2, -12.0f * t);
-    d2 = fmaf(-9.0f, t2, fmaf(6.0f, t, 3.0f));
-    d3 = 3.0f * t2;
-}
-
-__device__ __forceinline__ float to_f32(float v) { return v; }
-__device__ __forceinline__ float to_f32(__half v) { return __half2float(v); }
-
-// 4x4 tensor-product interpolation; b points at tap (x0-1, y0-1).
-template <typename Ptr>
-__device__ __forceinline__ float interp16(Ptr b, int64_t pitch, float x0, float x1, float x2, float x3, float y0,
-                                          float y1, float y2, float y3)
-{
-    const float r0 = fmaf(x3, to_f32(b[3]), fmaf(x2, to_f32(b[2]), fmaf(x1, to_f32(b[1]), x0 * to_f32(b[0]))));
-    b += pitch;
-    const float r1 = fmaf(x3, to_f32(b[3]), fmaf(x2, to_f32(b[2]), fmaf(x1, to_f32(b[1]), x0 * to_f32(b[0]))));
-    b += pitch;
-    const float r2 = fmaf(x3, to_f32(b[3]), fmaf(x2, to_f32(b[2]), fmaf(x1, to_f32(b[1]), x0 * to_f32(b[0]))));
-    b += pitch;
-    const float r3 = fmaf(x3, to_f32(b[3]), fmaf(x2, to_f32(b[2]), fmaf(x1, to_f32(b[1]), x0 * to_f32(b[0]))));
-    return fmaf(y3, r3, fmaf(y2, r2, fmaf(y1, r1, y0 * r0)));
-}
-
-// Map a ZNCC to an unsigned key whose integer order is the float order.
-__device__ __forceinline__ uint32_t ordered_bits(float f)
-{
-    const uint32_t u = __float_as_uint(f);
-    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-
-// Value of the lane chosen by DPP control CTRL (quad_perm, row mirrors), per 32-bit half.
-// (every control used here has a source lane for every lane and the row and bank
-// masks are full, so each lane is written and no previous value needs setting)
-template <int CTRL>
-__device__ __forceinline__ double dpp_read(double v)
-{
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-template <int CTRL>
-__device__ __forceinline__ float dpp_read(float v)
-{
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-
-// v + (v of the partner lane) where the partner sits in the other 16-lane row of a row
-// pair (permlane16 swap) or in the other 32-lane half (permlane32 swap).  The swap
-// returns the even-row (lower-half) value in one result and the odd-row (upper-half)
-// value in the other on every lane, so their sum is formed in the same order everywhere.
-__device__ __forceinline__ float pair_sum16(float v)
-{
-    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(v), __float_as_int(v), false, false);
-    return __int_as_float(r[0]) + __int_as_float(r[1]);
-}
-__device__ __forceinline__ float pair_sum32(float v)
-{
-    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_int(v), __float_as_int(v), false, false);
-    return __int_as_float(r[0]) + __int_as_float(r[1]);
-}
-__device__ __forceinline__ double pair_sum16(double v)
-{
-    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
-    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
-    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
-}
-__device__ __forceinline__ double pair_sum32(double v)
-{
-    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
-    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
-    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
-}
-
-// Sum over the 64 lanes of a wavefront, left in every lane.  Each step adds the value
-// of a partner lane under an involution (quad xor 1, quad xor 2, half-row mirror, row
-// mirror, row pairs, halves), so both partners form the same sum: every lane ends
-// with bitwise the same total.  No LDS traffic.
-template <typename V>
-__device__ __forceinline__ V wave_allreduce(V v)
-{
-    v += dpp_read<0xB1>(v);   // quad_perm [1,0,3,2]
-    v += dpp_read<0x4E>(v);   // quad_perm [2,3,0,1]
-    v += dpp_read<0x141>(v);  // row_half_mirror
-    v += dpp_read<0x140>(v);  // row_mirror
-    v = pair_sum16(v);
-    v = pair_sum32(v);
-    return v;
-}
 
 // All-reduce of NV values over the T threads of a workgroup: wavefront totals, then
 // summed in a fixed order from LDS (double buffered by `parity`, since one barrier
@@ -422,12 +289,6 @@ __device__ __forceinline__ void steepest(double (&J)[NP], double gx, double gy, 
     }
 }
 
-// Degenerate-case thresholds: a subset is flat when its RMS deviation is below
-// 1e-6 of its mean level; a Cholesky pivot is singular below 1e-10 of the
-// largest Hessian diagonal, each entry taken in the units of the convergence
-// norm (weights 1, h^2, h^4 for translation, gradient and curvature terms).
-constexpr double kFlatRel = 1e-6;
-constexpr double kSingularRel = 1e-10;
 
 // Slot of sum-group B entry i in the per-node cache: entries 0..NP-1 (sum J) go
 // to slots 3..3+NP-1, entries NP.. (sum J J^T, upper triangle by rows) to the
@@ -850,6 +711,22 @@ void launch_frame_stats(const RefView &R, const FrameState &F, hipStream_t s)
     k_frame_stats<<<static_cast<unsigned>(blocks), 256, 0, s>>>(R, F);
 }
 
+// Zero `words` 32-bit words (a kernel rather than a memset node, so the same
+// sequence may also run inside a captured graph).
+__global__ void k_zero32(uint32_t *p, int64_t words)
+{
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < words;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[i] = 0u;
+}
+
+void launch_zero32(void *p, int64_t words, hipStream_t s)
+{
+    if (words <= 0) return;
+    const int64_t blocks = std::min<int64_t>((words + 255) / 256, 1024);
+    k_zero32<<<static_cast<unsigned>(blocks), 256, 0, s>>>(static_cast<uint32_t *>(p), words);
+}
+
 // For each of n frames (device array), the size of the wave it runs at launch step
 // `step` (0 before its start or past its counts).
 __global__ void k_gather_next(const FrameState *frames, int n, int step, int32_t *out)
@@ -883,114 +760,6 @@ void launch_finalize(const RefView &R, const FrameState &F, int np, bool nan_unc
 {
     if (!nan_unconverged) return;
     k_finalize<<<static_cast<unsigned>((R.nodes + 255) / 256), 256, 0, s>>>(R, F, np);
-}
-
-// ---------------------------------------------------------------------------
-// Inverse-compositional update p <- p o dp^{-1} (FP64).
-// ---------------------------------------------------------------------------
-// Affine: with M(q) = [[1+q2, q3, q0], [q4, 1+q5, q1], [0, 0, 1]], the product
-// M(p) M(dp)^{-1} written so that every entry is formed from differences
-// p_j - dp_j (no "(1 + small) - 1" cancellation; exact when dp = 0).
-__device__ __forceinline__ void compose_affine(double (&p)[6], const double (&d)[6])
-{
-    // contraction is free here: d = 0 leaves p unchanged with or without it
-#pragma clang fp contract(fast)
-    const double a = 1.0 + d[2], b = d[3], c = d[4], e = 1.0 + d[5];
-    const double det = a * e - b * c;
-    // the reciprocal scales terms that are differences of order |dp|: FP32 suffices
-    const double r = static_cast<double>(1.0f / static_cast<float>(det));
-    // translation part of M(dp)^{-1}: -(M2^{-1}) (d0, d1)
-    const double tx = (b * d[1] - e * d[0]) * r;
-    const double ty = (c * d[0] - a * d[1]) * r;
-    const double n2 = (e * (p[2] - d[2]) - c * (p[3] - d[3])) * r;
-    const double n3 = ((p[3] - d[3]) + p[3] * d[2] - p[2] * d[3]) * r;
-    const double n4 = ((p[4] - d[4]) + p[4] * d[5] - p[5] * d[4]) * r;
-    const double n5 = (a * (p[5] - d[5]) - b * (p[4] - d[4])) * r;
-    const double n0 = p[0] + (1.0 + p[2]) * tx + p[3] * ty;
-    const double n1 = p[1] + p[4] * tx + (1.0 + p[5]) * ty;
-    p[0] = n0; p[1] = n1; p[2] = n2; p[3] = n3; p[4] = n4; p[5] = n5;
-}
-
-// Quadratic: lift q to the 6x6 matrix Q(q) acting on the monomials
-// [dx^2, dx dy, dy^2, dx, dy, 1] (each image monomial truncated at second
-// order); the update keeps the X and Y rows of Q(p) Q(dp)^{-1}, found by
-// solving Q(dp)^T r = (row of Q(p))^T with partial pivoting.
-__device__ __forceinline__ void lift(const double (&q)[12], double (&Q)[6][6])
-{
-    const double U = q[0], V = q[1], A = 1.0 + q[2], B = q[3], C = q[4], D = 1.0 + q[5];
-    const double a0 = q[6], a1 = q[7], a2 = q[8], b0 = q[9], b1 = q[10], b2 = q[11];
-    // X^2
-    Q[0][0] = A * A + 2.0 * U * a0; Q[0][1] = 2.0 * (A * B + U * a1); Q[0][2] = B * B + 2.0 * U * a2;
-    Q[0][3] = 2.0 * U * A; Q[0][4] = 2.0 * U * B; Q[0][5] = U * U;
-    // X Y
-    Q[1][0] = A * C + U * b0 + V * a0; Q[1][1] = A * D + B * C + U * b1 + V * a1; Q[1][2] = B * D + U * b2 + V * a2;
-    Q[1][3] = U * C + V * A; Q[1][4] = U * D + V * B; Q[1][5] = U * V;
-    // Y^2
-    Q[2][0] = C * C + 2.0 * V * b0; Q[2][1] = 2.0 * (C * D + V * b1); Q[2][2] = D * D + 2.0 * V * b2;
-    Q[2][3] = 2.0 * V * C; Q[2][4] = 2.0 * V * D; Q[2][5] = V * V;
-    // X, Y, 1
-    Q[3][0] = a0; Q[3][1] = a1; Q[3][2] = a2; Q[3][3] = A; Q[3][4] = B; Q[3][5] = U;
-    Q[4][0] = b0; Q[4][1] = b1; Q[4][2] = b2; Q[4][3] = C; Q[4][4] = D; Q[4][5] = V;
-    Q[5][0] = 0.0; Q[5][1] = 0.0; Q[5][2] = 0.0; Q[5][3] = 0.0; Q[5][4] = 0.0; Q[5][5] = 1.0;
-}
-
-// The elimination runs on a 6 x 8 working matrix in LDS (M, 48 doubles, one per
-// workgroup): its rows are picked by the pivot search at run time, which in
-// registers would force the whole matrix out to scratch memory.
-__device__ __forceinline__ void compose_quadratic(double (&p)[12], const double (&d)[12], double *M)
-{
-    {
-        double Qd[6][6];
-        lift(d, Qd);
-#pragma unroll
-        for (int i = 0; i < 6; ++i) {
-#pragma unroll
-            for (int j = 0; j < 6; ++j) M[i * 8 + j] = Qd[j][i];   // transpose
-        }
-    }
-    // right-hand sides: the X and Y rows of Q(p), i.e. (a0, a1, a2, A, B, U) and
-    // (b0, b1, b2, C, D, V) in the monomial order
-    M[0 * 8 + 6] = p[6];  M[1 * 8 + 6] = p[7];  M[2 * 8 + 6] = p[8];
-    M[3 * 8 + 6] = 1.0 + p[2]; M[4 * 8 + 6] = p[3]; M[5 * 8 + 6] = p[0];
-    M[0 * 8 + 7] = p[9];  M[1 * 8 + 7] = p[10]; M[2 * 8 + 7] = p[11];
-    M[3 * 8 + 7] = p[4];  M[4 * 8 + 7] = 1.0 + p[5]; M[5 * 8 + 7] = p[1];
-#pragma unroll
-    for (int col = 0; col < 6; ++col) {
-        int piv = col;
-        double best = fabs(M[col * 8 + col]);
-#pragma unroll
-        for (int r = col + 1; r < 6; ++r) {
-            const double v = fabs(M[r * 8 + col]);
-            if (v > best) { best = v; piv = r; }
-        }
-        if (piv != col) {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const double tv = M[col * 8 + k];
-                M[col * 8 + k] = M[piv * 8 + k];
-                M[piv * 8 + k] = tv;
-            }
-        }
-        const double inv = 1.0 / M[col * 8 + col];
-#pragma unroll
-        for (int r = 0; r < 6; ++r) {
-            if (r == col) continue;
-            const double fct = M[r * 8 + col] * inv;
-#pragma unroll
-            for (int k = col; k < 8; ++k) M[r * 8 + k] -= fct * M[col * 8 + k];
-        }
-    }
-    double x[6], y[6];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        x[i] = M[i * 8 + 6] / M[i * 8 + i];
-        y[i] = M[i * 8 + 7] / M[i * 8 + i];
-    }
-    p[0] = x[5]; p[1] = y[5];
-    p[2] = x[3] - 1.0; p[3] = x[4];
-    p[4] = y[3]; p[5] = y[4] - 1.0;
-    p[6] = x[0]; p[7] = x[1]; p[8] = x[2];
-    p[9] = y[0]; p[10] = y[1]; p[11] = y[2];
 }
 
 // ---------------------------------------------------------------------------
@@ -2024,7 +1793,8 @@ bool launch_wave(const FrameTable &F, int step, int np, int N, int tps, bool f64
     return false;
 }
 
-void launch_ref_nodes(const RefView &R, int np, int tps, double *cache, int8_t *flag, hipStream_t s)
+// false if no kernel is built for (np, tps, N): nothing is launched then
+bool launch_ref_nodes(const RefView &R, int np, int tps, double *cache, int8_t *flag, hipStream_t s)
 {
     const int P = pixels_per_thread(R.N, tps);
     if (tps < 64) {
@@ -2034,20 +1804,21 @@ void launch_ref_nodes(const RefView &R, int np, int tps, double *cache, int8_t *
     if (np == 6 && tps == LS_ && P == P_) {                                                                           \
         k_ref_nodes_packed<LS_, P_><<<grid, 64, 0, s>>>(R, cache, flag);                                              \
         k_ref_factor<6><<<static_cast<unsigned>((R.nodes + 255) / 256), 256, 0, s>>>(R, cache, flag);               \
-        return;                                                                                                        \
+        return true;                                                                                                   \
     }
         DIC_PACKED_CASES(X)
 #undef X
-        return;
+        return false;
     }
 #define X(NP_, T_, P_)                                                                                                \
     if (np == NP_ && tps == T_ && P == P_) {                                                                          \
         ref_nodes_inst<NP_, T_, P_>(R, cache, flag, s);                                                               \
-        return;                                                                                                        \
+        return true;                                                                                                   \
     }
     DIC_TP_CASES(6, X)
     DIC_TP_CASES(12, X)
 #undef X
+    return false;
 }
 
 bool supported_tps(int N, int tps)

@@ -30,6 +30,7 @@ NODE = dict(CONVERGED=0, NOT_REACHED=1, NOT_IN_ROI=2, MAX_ITER=3, LOW_ZNCC=4, OU
 # exported names, in the order include/dic.h declares them
 EXPORTS = ["dic_create", "dic_set_reference", "dic_grid_shape", "dic_correlate", "dic_correlate_batch",
            "dic_get_stats", "dic_destroy", "dic_last_error",
+           "dic_strain", "dic_vsg",
            "dic_server_create", "dic_server_add_reference", "dic_server_remove_reference", "dic_server_submit",
            "dic_server_step", "dic_server_poll", "dic_server_forget", "dic_server_get_stats", "dic_server_destroy",
            "dic_server_last_error"]
@@ -62,6 +63,14 @@ class DicStats(C.Structure):
                 ("threads_per_subset", C.c_int32), ("seed_du", C.c_int32), ("seed_dv", C.c_int32),
                 ("ms_total", C.c_double), ("ms_icgn", C.c_double), ("ms_prefilter", C.c_double),
                 ("ms_wave_kernels", C.c_double), ("wave_launches", C.c_int32)]
+
+
+class DicStrainParams(C.Structure):
+    _fields_ = [("window", C.c_int32), ("basis", C.c_int32), ("measure", C.c_int32)]
+
+
+STRAIN_BASIS = {"bilinear": 4, "biquadratic": 9}
+STRAIN_MEASURE = {"green_lagrange": 0, "hencky": 1, "euler_almansi": 2, "biot_right": 3, "biot_left": 4}
 
 
 class DicServerParams(C.Structure):
@@ -98,6 +107,9 @@ def load_library(path: str = LIB_PATH):
     L.dic_correlate.argtypes = [C.c_void_p, P(DicImage), P(DicSeed), C.c_int32, P(DicResult)]
     L.dic_correlate_batch.argtypes = [C.c_void_p, P(DicImage), C.c_int32, P(DicSeed), C.c_int32, P(DicResult)]
     L.dic_get_stats.argtypes = [C.c_void_p, P(DicStats)]
+    L.dic_strain.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                             P(DicStrainParams), C.c_void_p, C.c_void_p]
+    L.dic_vsg.argtypes = [C.c_int32, C.c_int32, C.c_int32]
     L.dic_destroy.argtypes = [C.c_void_p]
     L.dic_last_error.argtypes = [C.c_void_p]
     L.dic_last_error.restype = C.c_char_p
@@ -116,6 +128,7 @@ def load_library(path: str = LIB_PATH):
     for n in EXPORTS:
         if not n.endswith("last_error"):
             getattr(L, n).restype = C.c_int
+    L.dic_vsg.restype = C.c_int32
     _lib = L
     return L
 
@@ -166,6 +179,17 @@ def dic_correlate_batch(ctx, images: Sequence[DicImage], seeds: Sequence[DicSeed
     sds = (DicSeed * len(seeds))(*seeds)
     res = (DicResult * len(results))(*results)
     _check(ctx, load_library().dic_correlate_batch(ctx, ims, len(images), sds, nseeds, res))
+
+
+def dic_strain(ctx, u_ptr: int, v_ptr: int, status_ptr: int, nx: int, ny: int, step: int,
+               params: DicStrainParams, F_ptr: int, eps_ptr: int):
+    _check(ctx, load_library().dic_strain(ctx, C.c_void_p(u_ptr), C.c_void_p(v_ptr), C.c_void_p(status_ptr or 0),
+                                          int(nx), int(ny), int(step), C.byref(params), C.c_void_p(F_ptr),
+                                          C.c_void_p(eps_ptr)))
+
+
+def dic_vsg(window: int, step: int, subset_size: int) -> int:
+    return int(load_library().dic_vsg(int(window), int(step), int(subset_size)))
 
 
 def dic_get_stats(ctx) -> dict:
@@ -347,6 +371,22 @@ class Engine:
         outs, ress = zip(*[self._alloc() for _ in frames])
         dic_correlate_batch(self.ctx, [_image(f) for f in frames], flat, ns, list(ress))
         return list(outs)
+
+    def strain(self, u, v, status=None, *, step, window=5, basis="bilinear", measure="green_lagrange"):
+        """dic_strain on device displacement planes u, v [ny][nx] (e.g. a result's p[0], p[1])."""
+        import torch
+        for t in (u, v):
+            if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.dim() == 2):
+                raise ValueError("u and v must be contiguous float32 device tensors [ny][nx]")
+        if status is not None and not (status.is_cuda and status.dtype == torch.int8 and status.is_contiguous()):
+            raise ValueError("status must be a contiguous int8 device tensor")
+        ny, nx = u.shape
+        F = torch.empty((4, ny, nx), dtype=torch.float32, device=u.device)
+        eps = torch.empty((3, ny, nx), dtype=torch.float32, device=u.device)
+        prm = DicStrainParams(int(window), STRAIN_BASIS[basis], STRAIN_MEASURE[measure])
+        dic_strain(self.ctx, u.data_ptr(), v.data_ptr(), status.data_ptr() if status is not None else 0, nx, ny,
+                   step, prm, F.data_ptr(), eps.data_ptr())
+        return {"F": F, "eps": eps}
 
     def stats(self) -> dict:
         return dic_get_stats(self.ctx)

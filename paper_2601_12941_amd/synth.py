@@ -271,6 +271,49 @@ def make_pair(W, H, nblobs, sigma, amp, field: Field, noise_sigma, bits, seed_bl
                 roi_from_field(W, H, field, roi_margin), field, bits)
 
 
+def noise_frames(w, nframes):
+    """Reference plus `nframes` deformed frames of workload `w` that differ only
+    in their noise (noise seeds seed_noise_def + i; frame 0 is w.pair()'s
+    deformed image), and the ROI.  The blobs are rendered once."""
+    X, Y, S, A = draw_blobs(w.W, w.H, w.nblobs, w.sigma, w.amp, w.seed_blobs)
+    render = _render_blobs_large if w.W * w.H > _LARGE else _render_blobs
+    f = w.field()
+    u, v = f(X, Y)
+    ref = _finish(render(w.W, w.H, X, Y, S, A), w.noise, w.seed_noise_ref, w.bits)
+    clean = render(w.W, w.H, X + u, Y + v, S, A)
+    frames = [_finish(clean, w.noise, w.seed_noise_def + i, w.bits) for i in range(nframes)]
+    return ref, frames, roi_from_field(w.W, w.H, f)
+
+
+def displacement_grid(nx, ny, step, kind="smooth", noise=0.0, invalid=0.0, seed=0):
+    """Seeded displacement fields u, v [ny][nx] (float32) on a node grid of the
+    given step, and a status array (int8, 0 = valid, 3 = not converged) with a
+    fraction `invalid` of invalid nodes: inputs for the strain step.
+    kinds: "smooth" (sinusoids and a quadratic, strain ~1e-2), "rotation"
+    (rotation by 0.3 rad with 4 % / -2 % stretch about the grid centre), "shear"
+    (simple shear 0.1)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    X, Y = np.meshgrid(np.arange(nx) * float(step), np.arange(ny) * float(step))
+    Xc, Yc = X - X.mean(), Y - Y.mean()
+    if kind == "smooth":
+        u = 0.8 + 0.01 * Xc - 0.004 * Yc + 2e-5 * Xc * Xc + 0.3 * np.sin(2 * np.pi * Y / 400.0)
+        v = -0.3 + 0.006 * Xc + 0.015 * Yc - 3e-5 * Xc * Yc + 0.2 * np.cos(2 * np.pi * X / 300.0)
+    elif kind == "rotation":
+        c, s = np.cos(0.3), np.sin(0.3)
+        a, d = 1.04, 0.98
+        u = (c * a - 1.0) * Xc - s * d * Yc
+        v = s * a * Xc + (c * d - 1.0) * Yc
+    elif kind == "shear":
+        u, v = 0.1 * Yc, 0.0 * Xc
+    else:
+        raise ValueError(kind)
+    if noise > 0:
+        u = u + rng.normal(0.0, noise, u.shape)
+        v = v + rng.normal(0.0, noise, v.shape)
+    status = np.where(rng.uniform(size=u.shape) < invalid, 3, 0).astype(np.int8)
+    return u.astype(np.float32), v.astype(np.float32), status
+
+
 def grid_shape(W, H, N, step):
     """Nodes at x_c = h + i*step, i < nx = floor((W-N)/step)+1 (y likewise), h=(N-1)/2."""
     nx = (W - N) // step + 1 if W >= N else 0

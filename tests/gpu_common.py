@@ -38,26 +38,38 @@ def oracle_run(pair, w, **over):
     return oracle.correlate(pair.ref, pair.deformed, pair.roi, seeds=w.seeds, threads=8, **prm)
 
 
-def compare(g, o, npar=6, tol_uv=TOL_UV, tol_zncc=TOL_ZNCC, status_agree=STATUS_AGREE):
-    """Element-by-element comparison; returns a report dict and asserts the bar."""
+def compare(g, o, npar=6, tol_uv=TOL_UV, tol_zncc=TOL_ZNCC, status_agree=STATUS_AGREE, wave_agree=None):
+    """Element-by-element comparison; returns a report dict and asserts the bar.
+
+    Every Eq. (5) parameter is held to the displacement bar in pixels at the
+    subset edge: |dp0|, |dp1| <= tol_uv, |dp_j| h <= tol_uv for the gradient
+    terms p2..p5 and |dp_j| h^2 <= tol_uv for the quadratic terms p6..p11
+    (h = (N-1)/2; N is read from the grid: nodes sit h + i*step apart from
+    the edge, so it is passed in through the oracle's result).  Wave indices
+    must agree on the nodes both sides converge (a status mismatch upstream
+    can move the breadth-first distance of the nodes behind it)."""
     gs = g["status"].astype(np.int32)
     os_ = o["status"]
     active = os_ != ST["NOT_IN_ROI"]
     assert np.array_equal(gs == ST["NOT_IN_ROI"], ~active), "active-node maps differ"
     agree = (gs == os_)[active].mean() if active.any() else 1.0
     both = (gs == ST["CONVERGED"]) & (os_ == ST["CONVERGED"])
+    h = (o["subset_size"] - 1) / 2.0
+    scale = np.array([1.0, 1.0] + [h] * 4 + [h * h] * 6)[:npar]
     du = np.abs(g["p"][0] - o["p"][0])[both]
     dv = np.abs(g["p"][1] - o["p"][1])[both]
     dz = np.abs(g["zncc"] - o["zncc"])[both]
-    dp = np.abs(g["p"][:npar] - o["p"][:npar])[:, both]
+    dp = (np.abs(g["p"][:npar] - o["p"][:npar])[:, both] * scale[:, None]) if both.any() else np.zeros((npar, 0))
     wave_eq = (g["wave"] == o["wave"])[both].mean() if both.any() else 1.0
     rep = dict(active=int(active.sum()), both_converged=int(both.sum()), status_agree=float(agree),
                max_du=float(du.max()) if du.size else 0.0, max_dv=float(dv.max()) if dv.size else 0.0,
                p999_duv=float(np.percentile(np.maximum(du, dv), 99.9)) if du.size else 0.0,
-               max_dzncc=float(dz.max()) if dz.size else 0.0, max_dp=dp.max(axis=1).tolist() if dp.size else [],
-               wave_equal=float(wave_eq))
+               max_dzncc=float(dz.max()) if dz.size else 0.0,
+               max_dp_px=dp.max(axis=1).tolist() if dp.size else [], wave_equal=float(wave_eq))
     print("parity:", rep, flush=True)
     assert agree >= status_agree, rep
     assert rep["max_du"] <= tol_uv and rep["max_dv"] <= tol_uv, rep
+    assert all(x <= tol_uv for x in rep["max_dp_px"]), rep
     assert rep["max_dzncc"] <= tol_zncc, rep
+    assert wave_eq >= (status_agree if wave_agree is None else wave_agree), rep
     return rep

@@ -18,7 +18,7 @@ HEADER = os.path.join(ROOT, "include", "dic.h")
 def declared_functions():
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\*?\s*(dic_[a-z_]+)\s*\(", txt, flags=re.M)
+    return re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(dic_[a-z_]+)\s*\(", txt, flags=re.M)
 
 
 def test_header_declares_the_binding_names():

@@ -50,7 +50,8 @@ def test_zero_displacement_is_exactly_zero():
     assert np.all(g["status"][act] == ST["CONVERGED"])
     assert np.all(g["p"][:, act] == 0.0)
     assert np.all(g["iters"][act] == 1)
-    assert np.abs(g["zncc"][act] - 1.0).max() <= 1e-6
+    # equal reference and deformed sums give a ratio of 1 and a ZNCC of exactly 1
+    assert np.all(g["zncc"][act] == 1.0)
 
 
 def test_repeat_runs_are_bitwise_identical(c1):
@@ -61,18 +62,17 @@ def test_repeat_runs_are_bitwise_identical(c1):
         assert np.array_equal(a[k], b[k]), k
 
 
-def test_batch_equals_plain():
+@pytest.mark.parametrize("nframes", [3, 8, 16])
+def test_batch_equals_plain(nframes):
+    # 8 and 16 frames take the kernel's frame-to-XCD affinity (every 8th frame on
+    # one XCD group), 3 frames the plain grid stride; both must give every frame
+    # bitwise the results of its own plain call
     import torch
     from paper_2601_12941_amd import dic
     w = synth.workload("c1", size=256)
-    pair = w.pair()
-    frames = [pair.deformed]
-    for s in (1004, 1005):
-        frames.append(synth.make_pair(w.W, w.H, w.nblobs, w.sigma, w.amp, w.field(), w.noise, w.bits, w.seed_blobs,
-                                      w.seed_noise_ref, s).deformed)
+    ref, frames, roi = synth.noise_frames(w, nframes)
     eng = dic.Engine(0)
-    roi = torch.from_numpy(pair.roi).cuda()
-    eng.set_reference(dic.to_device_image(pair.ref), roi, **w.params())
+    eng.set_reference(dic.to_device_image(ref), torch.from_numpy(roi).cuda(), **w.params())
     plain = [eng.correlate(dic.to_device_image(f), w.seeds) for f in frames]
     batch = eng.correlate_batch([dic.to_device_image(f) for f in frames], w.seeds)
     torch.cuda.synchronize()
