@@ -22,6 +22,7 @@ ST = dict(CONVERGED=0, NOT_REACHED=1, NOT_IN_ROI=2, MAX_ITER=3, LOW_ZNCC=4, OUT_
           FLAT_REF=6, FLAT_DEF=7, SINGULAR=8, NAN=9)
 ORDER = dict(wave=0, sequential=1)
 GUESS = dict(extrapolate=0, copy=1)
+COST = dict(znssd=0, nssd=1, ssd=2)
 
 _lib = None
 
@@ -50,13 +51,13 @@ def lib():
         L.orc_compose.restype = C.c_int
         L.orc_transfer_guess.argtypes = [dp, C.c_int, C.c_double, C.c_double, C.c_int, dp]
         L.orc_icgn_single.argtypes = [dp, dp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, C.c_double,
-                                      C.c_double, C.c_double, dp, dp, dp, ip, ip]
+                                      C.c_double, C.c_double, dp, dp, dp, ip, ip, C.c_int, C.c_double]
         L.orc_seed_single.argtypes = [dp, dp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                       C.c_double, C.c_double, ip, ip, dp]
         L.orc_seed_single.restype = C.c_int
         L.orc_correlate.argtypes = [dp, dp, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int,
                                     C.c_double, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, dp, C.c_int, C.c_int,
-                                    dp, dp, ip, ip, ip, dp]
+                                    dp, dp, ip, ip, ip, dp, C.c_int, C.c_double]
         L.orc_correlate.restype = C.c_long
         _lib = L
     return _lib
@@ -115,8 +116,10 @@ def transfer_guess(pm, npar, ddx, ddy, mode="extrapolate"):
     return out[:npar]
 
 
-def icgn(ref, deformed, xc, yc, p_init, N, npar=6, tol=1e-4, max_iter=50, zncc_min=0.7):
-    """IC-GN of one subset centred at (xc, yc) from p_init.  Returns (p, zncc, iters, status)."""
+def icgn(ref, deformed, xc, yc, p_init, N, npar=6, tol=1e-4, max_iter=50, zncc_min=0.7, cost="znssd",
+         lm_lambda=0.0):
+    """IC-GN (or, with lm_lambda > 0, Levenberg-Marquardt) of one subset centred at
+    (xc, yc) from p_init on the chosen cost.  Returns (p, zncc, iters, status)."""
     ref = _f64(ref)
     de = _f64(deformed)
     H, W = ref.shape
@@ -126,7 +129,8 @@ def icgn(ref, deformed, xc, yc, p_init, N, npar=6, tol=1e-4, max_iter=50, zncc_m
     z = np.zeros(1)
     it = np.zeros(1, np.int32)
     st = np.zeros(1, np.int32)
-    lib().orc_icgn_single(ref, de, W, H, N, npar, tol, max_iter, zncc_min, float(xc), float(yc), pi, p, z, it, st)
+    lib().orc_icgn_single(ref, de, W, H, N, npar, tol, max_iter, zncc_min, float(xc), float(yc), pi, p, z, it, st,
+                          COST[cost], float(lm_lambda))
     return p[:npar], float(z[0]), int(it[0]), int(st[0])
 
 
@@ -144,7 +148,7 @@ def seed_search(ref, deformed, xc, yc, N, R, u0=0.0, v0=0.0):
 
 
 def correlate(ref, deformed, roi=None, *, subset_size, step, shape=6, tol=1e-4, max_iter=50, zncc_min=0.7,
-              seed_radius=8, seeds, order="wave", guess="extrapolate", threads=1):
+              seed_radius=8, seeds, order="wave", guess="extrapolate", threads=1, cost="znssd", lm_lambda=0.0):
     """Reliability-guided correlation of one pair.
 
     seeds: iterable of (x, y, u0, v0).  Returns a dict of [ny][nx] arrays
@@ -176,7 +180,7 @@ def correlate(ref, deformed, roi=None, *, subset_size, step, shape=6, tol=1e-4, 
     ns = lib().orc_correlate(ref, de, W, H, roi_ptr, int_pix, N, step, shape, tol, max_iter, zncc_min, seed_radius,
                              GUESS[guess], ORDER[order], _f64(sd.ravel()) if len(sd) else np.zeros(4), len(sd),
                              int(threads), p.reshape(-1), z.reshape(-1), it.reshape(-1), st.reshape(-1),
-                             wv.reshape(-1), so.reshape(-1))
+                             wv.reshape(-1), so.reshape(-1), COST[cost], float(lm_lambda))
     dt = time.perf_counter() - t0
     if ns < 0:
         raise ValueError("no seed could be placed on an active node")

@@ -52,6 +52,8 @@ enum {
 
 enum { ORDER_WAVE = 0, ORDER_SEQUENTIAL = 1 };
 enum { GUESS_EXTRAPOLATE = 0, GUESS_COPY = 1 };
+/* cost functions of Sec. 2.2: Eq. (4) (the default), Eq. (3), Eq. (2) */
+enum { COST_ZNSSD = 0, COST_NSSD = 1, COST_SSD = 2 };
 
 #define NPMAX 12 /* quadratic shape: p0..p11 */
 
@@ -347,6 +349,8 @@ typedef struct {
     double zncc_min;
     int seed_radius;
     int guess_mode;
+    int cost;          /* COST_* */
+    double lm_lambda;  /* 0: Gauss-Newton; > 0: initial Levenberg-Marquardt damping */
 } orc_problem;
 
 typedef struct {
@@ -389,16 +393,33 @@ static double dp_norm(const double *dp, int np, double h)
  *   7. p <- p o dp^{-1};
  *   8. NaN anywhere -> NAN; |dp| < tol -> converged (LOW_ZNCC if ZNCC < zncc_min).
  * Without convergence after max_iter iterations -> MAX_ITER.
+ *
+ * Other costs of Sec. 2.2 (same loop, same Gauss-Newton structure):
+ *   NSSD, Eq. (3):  r_i = f_i - (|f|/|g|) g_i with |f| = sqrt(sum f_i^2) (no
+ *                   mean removed), cost sum r_i^2 / |f|^2, H = sum J_i^T J_i;
+ *   SSD,  Eq. (2):  r_i = f_i - g_i, cost sum r_i^2, H = sum J_i^T J_i.
+ * The reported coefficient is the ZNCC of step 5 for every cost.
+ *
+ * Levenberg-Marquardt (Sec. 2.2 names it as the optimiser; Gauss-Newton is
+ * its zero-damping case), with lambda > 0: the increment solves
+ * (H + lambda diag(H)) dp = -b.  Iteration 1 accepts its evaluation; a later
+ * evaluation whose cost is not above the last accepted one is accepted and
+ * divides lambda by 10, otherwise it is rejected: lambda is multiplied by 10
+ * and the step is recomputed from the last accepted p and b.  The convergence
+ * test is the same; the ZNCC reported is the last accepted one.
  */
 void orc_icgn_node(const orc_problem *P, double xc, double yc, const double *p_init, orc_node_result *res)
 {
     const int N = P->N, np = P->np, n = N * N;
     const int h = (N - 1) / 2;
     double *fbar = (double *)malloc(sizeof(double) * (size_t)n);
+    double *fraw = (double *)malloc(sizeof(double) * (size_t)n);
+    double *graw = (double *)malloc(sizeof(double) * (size_t)n);
     double *J = (double *)malloc(sizeof(double) * (size_t)n * NPMAX);
     double *g = (double *)malloc(sizeof(double) * (size_t)n);
-    double Hm[NPMAX * NPMAX], L[NPMAX * NPMAX];
-    double p[NPMAX];
+    double Hm[NPMAX * NPMAX], L[NPMAX * NPMAX], Ld[NPMAX * NPMAX];
+    double p[NPMAX], p_acc[NPMAX], b_acc[NPMAX];
+    double lam = P->lm_lambda, best = 0.0, z_acc = 0.0;
     memset(p, 0, sizeof(p));
     for (int j = 0; j < np; ++j) p[j] = p_init[j];
     res->zncc = 0.0;
@@ -410,6 +431,7 @@ void orc_icgn_node(const orc_problem *P, double xc, double yc, const double *p_i
         int dy = i / N - h, dx = i % N - h;
         double gx, gy;
         fbar[i] = orc_eval(P->fc, P->W, P->H, xc + dx, yc + dy, &gx, &gy);
+        fraw[i] = fbar[i];
         fsum += fbar[i];
         double jx[NPMAX], jy[NPMAX];
         shape_jac(np, dx, dy, jx, jy);
@@ -429,13 +451,16 @@ void orc_icgn_node(const orc_problem *P, double xc, double yc, const double *p_i
     }
     /* Gauss-Newton Hessian of the zero-mean criterion: the warped reference
      * subset's mean moves with the increment, so its Jacobian is the
-     * mean-centred J.  b = sum J^T r needs no centring because sum r = 0. */
+     * mean-centred J.  b = sum J^T r needs no centring because sum r = 0.
+     * NSSD and SSD remove no mean: their Hessian is the uncentred sum. */
     double Jm[NPMAX];
     for (int k = 0; k < np; ++k) {
         double s = 0.0;
         for (int i = 0; i < n; ++i) s += J[i * NPMAX + k];
-        Jm[k] = s / n;
+        Jm[k] = P->cost == COST_ZNSSD ? s / n : 0.0;
     }
+    double ff = 0.0; /* |f|^2 of NSSD */
+    for (int i = 0; i < n; ++i) ff += fraw[i] * fraw[i];
     for (int a = 0; a < np; ++a)
         for (int b = 0; b < np; ++b) {
             double s = 0.0;
@@ -477,8 +502,12 @@ void orc_icgn_node(const orc_problem *P, double xc, double yc, const double *p_i
             g[i] = orc_eval(P->gc, P->W, P->H, x, y, NULL, NULL);
         }
         /* 3: two-pass mean and norm */
-        double gs = 0.0;
-        for (int i = 0; i < n; ++i) gs += g[i];
+        double gs = 0.0, gg = 0.0;
+        for (int i = 0; i < n; ++i) {
+            graw[i] = g[i];
+            gs += g[i];
+            gg += g[i] * g[i];
+        }
         double gm = gs / n;
         double gss = 0.0;
         for (int i = 0; i < n; ++i) {
@@ -494,25 +523,60 @@ void orc_icgn_node(const orc_problem *P, double xc, double yc, const double *p_i
         double dg = sqrt(gss);
         /* 4-6 */
         double ratio = df / dg, rr = 0.0, b[NPMAX];
+        double nratio = sqrt(ff / gg), cr = 0.0; /* NSSD's |f|/|g|; the chosen cost's sum of r^2 */
         memset(b, 0, sizeof(b));
         for (int i = 0; i < n; ++i) {
             double r = fbar[i] - ratio * g[i];
             rr += r * r;
+            if (P->cost == COST_NSSD) r = fraw[i] - nratio * graw[i];
+            else if (P->cost == COST_SSD) r = fraw[i] - graw[i];
+            cr += r * r;
             for (int k = 0; k < np; ++k) b[k] += J[i * NPMAX + k] * r;
         }
         double znssd = rr / (df * df);
         res->zncc = 1.0 - 0.5 * znssd;
+        if (lam > 0.0) {
+            const double cval = P->cost == COST_ZNSSD ? znssd : (P->cost == COST_NSSD ? cr / ff : cr);
+            if (it == 1 || cval <= best) {
+                if (it > 1) lam *= 0.1;
+                best = cval;
+                z_acc = res->zncc;
+                memcpy(p_acc, p, sizeof(p));
+                memcpy(b_acc, b, sizeof(b));
+            } else {
+                lam *= 10.0;
+                res->zncc = z_acc;
+                memcpy(p, p_acc, sizeof(p));
+                memcpy(b, b_acc, sizeof(b));
+            }
+        }
         double y[NPMAX], dp[NPMAX];
         memset(dp, 0, sizeof(dp));
+        const double *Ls = L;
+        if (lam > 0.0) {
+            /* Cholesky of H + lambda diag(H) */
+            for (int j = 0; j < np; ++j) {
+                double d = Hm[j * np + j] * (1.0 + lam);
+                for (int k = 0; k < j; ++k) d -= Ld[j * np + k] * Ld[j * np + k];
+                if (!(d > 0.0)) { res->status = ST_SINGULAR; goto done; }
+                Ld[j * np + j] = sqrt(d);
+                for (int i = j + 1; i < np; ++i) {
+                    double t = Hm[i * np + j];
+                    for (int k = 0; k < j; ++k) t -= Ld[i * np + k] * Ld[j * np + k];
+                    Ld[i * np + j] = t / Ld[j * np + j];
+                }
+            }
+            Ls = Ld;
+        }
         for (int j = 0; j < np; ++j) {
             double s = b[j];
-            for (int k = 0; k < j; ++k) s -= L[j * np + k] * y[k];
-            y[j] = s / L[j * np + j];
+            for (int k = 0; k < j; ++k) s -= Ls[j * np + k] * y[k];
+            y[j] = s / Ls[j * np + j];
         }
         for (int j = np - 1; j >= 0; --j) {
             double s = y[j];
-            for (int k = j + 1; k < np; ++k) s -= L[k * np + j] * dp[k];
-            dp[j] = s / L[j * np + j];
+            for (int k = j + 1; k < np; ++k) s -= Ls[k * np + j] * dp[k];
+            dp[j] = s / Ls[j * np + j];
         }
         for (int j = 0; j < np; ++j) dp[j] = -dp[j];
         /* 7: p <- p o dp^-1 */
@@ -534,6 +598,8 @@ done:
     memset(res->p, 0, sizeof(res->p));
     for (int j = 0; j < np; ++j) res->p[j] = p[j];
     free(fbar);
+    free(fraw);
+    free(graw);
     free(J);
     free(g);
 }
@@ -730,7 +796,8 @@ static heap_item heap_pop(heap_item *h, long *sz)
 long orc_correlate(const double *ref, const double *def, int W, int H, const uint8_t *roi, int int_pixels, int N,
                    int step, int np, double tol, int max_iter, double zncc_min, int seed_radius, int guess_mode,
                    int order, const double *seeds, int nseeds, int nthreads, double *p_out, double *zncc_out,
-                   int32_t *iters_out, int32_t *status_out, int32_t *wave_out, double *seed_out)
+                   int32_t *iters_out, int32_t *status_out, int32_t *wave_out, double *seed_out, int cost,
+                   double lm_lambda)
 {
     orc_problem P;
     memset(&P, 0, sizeof(P));
@@ -739,6 +806,7 @@ long orc_correlate(const double *ref, const double *def, int W, int H, const uin
     P.ny = H >= N ? (H - N) / step + 1 : 0;
     P.tol = tol; P.max_iter = max_iter; P.zncc_min = zncc_min; P.seed_radius = seed_radius;
     P.guess_mode = guess_mode; P.int_pixels = int_pixels; P.fraw = ref; P.graw = def;
+    P.cost = cost; P.lm_lambda = lm_lambda;
     const long nn = (long)P.nx * P.ny;
     const int h = (N - 1) / 2;
 #ifdef _OPENMP
@@ -910,11 +978,12 @@ void orc_eval_many(const double *coef, int W, int H, const double *x, const doub
 /* One subset from a given start; images are raw pixels, prefiltered here. */
 void orc_icgn_single(const double *ref, const double *def, int W, int H, int N, int np, double tol, int max_iter,
                      double zncc_min, double xc, double yc, const double *p_init, double *p_out, double *zncc,
-                     int32_t *iters, int32_t *status)
+                     int32_t *iters, int32_t *status, int cost, double lm_lambda)
 {
     orc_problem P;
     memset(&P, 0, sizeof(P));
     P.W = W; P.H = H; P.N = N; P.np = np; P.tol = tol; P.max_iter = max_iter; P.zncc_min = zncc_min;
+    P.cost = cost; P.lm_lambda = lm_lambda;
     double *fc = (double *)malloc(sizeof(double) * (size_t)W * H);
     double *gc = (double *)malloc(sizeof(double) * (size_t)W * H);
     orc_prefilter_2d(ref, W, H, fc);
