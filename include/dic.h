@@ -171,6 +171,29 @@ dic_status dic_correlate(dic_ctx *c, const dic_image *def, const dic_seed *seeds
 dic_status dic_correlate_batch(dic_ctx *c, const dic_image *defs, int32_t nframes, const dic_seed *seeds,
                                int32_t nseeds, dic_result *outs);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * correlation as dic_correlate, bitwise, with no hipMalloc, hipFree or other
+ * allocating call.  Per-frame scratch lives in one library-owned device array
+ * of dic_noalloc_scratch_bytes() bytes (64 MiB) per device, held until the
+ * process ends; the context's own buffers come from dic_create and
+ * dic_set_reference, the result arrays from the caller.  At most 64 seeds.
+ * A reference whose scratch does not fit (deformed coefficients, parent keys,
+ * frontier lists and wave sizes: about 36 bytes per pixel-grid node plus 4 (2
+ * with FP16) bytes per padded pixel; a 2048 x 2048 image at step 2 needs
+ * 38 MB) is refused with DIC_E_INVAL before any work is queued.
+ * Every call on one device shares that device's array and leaves its last
+ * contents there (each call clears what it needs): calls that overlap on one
+ * device, from any context or stream, race and must be serialised by the
+ * caller.
+ */
+dic_status dic_correlate_noalloc(dic_ctx *c, const dic_image *def, const dic_seed *seeds, int32_t nseeds,
+                                 dic_result *out);
+
+/* Bytes of the per-device scratch array dic_correlate_noalloc uses. */
+int64_t dic_noalloc_scratch_bytes(void);
+
 /* Counters and timings of the last call. */
 dic_status dic_get_stats(const dic_ctx *c, dic_stats *out);
 

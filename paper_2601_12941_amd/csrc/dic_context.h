@@ -28,6 +28,11 @@ inline size_t pixel_size(int pixel) { return pixel == DIC_PIX_U8 ? 1 : (pixel ==
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
+// Device address of the allocation-free entry point's scratch array on
+// `device` (dic_noalloc.hip); nullptr if the lookup fails.
+void *noalloc_scratch(int device);
+constexpr size_t kNoallocStageBytes = 4096;
+
 // Shared steps of the correlate entry points (dic_engine.hip).
 dic_status check_correlate_args(dic_ctx *c, const dic_image *defs, int32_t nframes, const dic_seed *seeds,
                                 int32_t nseeds, const dic_result *outs);
@@ -83,6 +88,8 @@ struct dic_ctx {
     RefView *d_view = nullptr;   // device copy of view(), read by the wave kernel
     int32_t *h_pinned = nullptr;
     unsigned long long *h_stats = nullptr;  // pinned: 4 counters per frame, then the last frame's seed shift
+    void *noalloc_base = nullptr;           // this device's scratch array (dic_correlate_noalloc)
+    int32_t *h_noalloc = nullptr;           // pinned staging of dic_correlate_noalloc (seeds, frame record)
     double *d_strain_w = nullptr;           // least-squares derivative weights of dic_strain
     hipEvent_t ev[4] = {};
     std::vector<hipEvent_t> chunk_ev;

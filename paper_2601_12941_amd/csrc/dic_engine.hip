@@ -35,12 +35,16 @@ dic_status dic_create(dic_ctx **out, int device, void *hip_stream)
         }
     if (hipHostMalloc(reinterpret_cast<void **>(&c->h_pinned), 64 * sizeof(int32_t)) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&c->h_stats), sizeof(unsigned long long) * (4 * kMaxFrames + 2)) !=
-            hipSuccess) {
+            hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&c->h_noalloc), kNoallocStageBytes) != hipSuccess) {
         if (c->h_pinned) (void)hipHostFree(c->h_pinned);
         if (c->h_stats) (void)hipHostFree(c->h_stats);
         delete c;
         return DIC_E_DEVICE;
     }
+    // the allocation-free entry point's scratch array on this device (looked up
+    // once per device; dic_correlate_noalloc reports a failed lookup)
+    c->noalloc_base = noalloc_scratch(device);
     *out = c;
     return DIC_OK;
 }
@@ -60,6 +64,7 @@ dic_status dic_destroy(dic_ctx *c)
     dfree(c->d_strain_w);
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
     if (c->h_stats) (void)hipHostFree(c->h_stats);
+    if (c->h_noalloc) (void)hipHostFree(c->h_noalloc);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto &e : c->chunk_ev) (void)hipEventDestroy(e);

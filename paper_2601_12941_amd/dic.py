@@ -29,7 +29,7 @@ NODE = dict(CONVERGED=0, NOT_REACHED=1, NOT_IN_ROI=2, MAX_ITER=3, LOW_ZNCC=4, OU
 
 # exported names, in the order include/dic.h declares them
 EXPORTS = ["dic_create", "dic_set_reference", "dic_grid_shape", "dic_correlate", "dic_correlate_batch",
-           "dic_get_stats", "dic_destroy", "dic_last_error",
+           "dic_correlate_noalloc", "dic_noalloc_scratch_bytes", "dic_get_stats", "dic_destroy", "dic_last_error",
            "dic_strain", "dic_vsg",
            "dic_server_create", "dic_server_add_reference", "dic_server_remove_reference", "dic_server_submit",
            "dic_server_step", "dic_server_poll", "dic_server_forget", "dic_server_get_stats", "dic_server_destroy",
@@ -106,6 +106,8 @@ def load_library(path: str = LIB_PATH):
     L.dic_grid_shape.argtypes = [C.c_void_p] + [P(C.c_int32)] * 5
     L.dic_correlate.argtypes = [C.c_void_p, P(DicImage), P(DicSeed), C.c_int32, P(DicResult)]
     L.dic_correlate_batch.argtypes = [C.c_void_p, P(DicImage), C.c_int32, P(DicSeed), C.c_int32, P(DicResult)]
+    L.dic_correlate_noalloc.argtypes = [C.c_void_p, P(DicImage), P(DicSeed), C.c_int32, P(DicResult)]
+    L.dic_noalloc_scratch_bytes.argtypes = []
     L.dic_get_stats.argtypes = [C.c_void_p, P(DicStats)]
     L.dic_strain.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
                              P(DicStrainParams), C.c_void_p, C.c_void_p]
@@ -128,6 +130,7 @@ def load_library(path: str = LIB_PATH):
     for n in EXPORTS:
         if not n.endswith("last_error"):
             getattr(L, n).restype = C.c_int
+    L.dic_noalloc_scratch_bytes.restype = C.c_int64
     L.dic_vsg.restype = C.c_int32
     _lib = L
     return L
@@ -179,6 +182,15 @@ def dic_correlate_batch(ctx, images: Sequence[DicImage], seeds: Sequence[DicSeed
     sds = (DicSeed * len(seeds))(*seeds)
     res = (DicResult * len(results))(*results)
     _check(ctx, load_library().dic_correlate_batch(ctx, ims, len(images), sds, nseeds, res))
+
+
+def dic_correlate_noalloc(ctx, image: DicImage, seeds: Sequence[DicSeed], result: DicResult):
+    arr = (DicSeed * len(seeds))(*seeds)
+    _check(ctx, load_library().dic_correlate_noalloc(ctx, C.byref(image), arr, len(seeds), C.byref(result)))
+
+
+def dic_noalloc_scratch_bytes() -> int:
+    return int(load_library().dic_noalloc_scratch_bytes())
 
 
 def dic_strain(ctx, u_ptr: int, v_ptr: int, status_ptr: int, nx: int, ny: int, step: int,
@@ -356,6 +368,17 @@ class Engine:
     def correlate(self, deformed, seeds):
         out, res = self._alloc()
         dic_correlate(self.ctx, _image(deformed), self._seeds(seeds), res)
+        return out
+
+    def correlate_noalloc(self, deformed, seeds, out=None):
+        """dic_correlate_noalloc into caller-owned result tensors (allocated here
+        when `out` is None, as a caller would before entering its loop)."""
+        if out is None:
+            out, res = self._alloc()
+        else:
+            res = DicResult(out["p"].data_ptr(), out["zncc"].data_ptr(), out["iters"].data_ptr(),
+                            out["status"].data_ptr(), out["wave"].data_ptr())
+        dic_correlate_noalloc(self.ctx, _image(deformed), self._seeds(seeds), res)
         return out
 
     def correlate_batch(self, frames, seeds):
