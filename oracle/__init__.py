@@ -16,6 +16,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dic_oracle.c")
+_SRC_MW = os.path.join(_HERE, "mw_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 ST = dict(CONVERGED=0, NOT_REACHED=1, NOT_IN_ROI=2, MAX_ITER=3, LOW_ZNCC=4, OUT_OF_BOUNDS=5,
@@ -29,10 +30,11 @@ _lib = None
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (FP64, no contraction, OpenMP over wave members)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    stale = not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in (_SRC, _SRC_MW))
+    if force or stale:
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-fopenmp", "-o", tmp, _SRC,
-                               "-lm"])
+                               _SRC_MW, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -59,6 +61,19 @@ def lib():
                                     C.c_double, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, dp, C.c_int, C.c_int,
                                     dp, dp, ip, ip, ip, dp, C.c_int, C.c_double]
         L.orc_correlate.restype = C.c_long
+        u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
+        L.orc_fft2.argtypes = [dp, dp, C.c_int, C.c_int]
+        L.orc_phase_corr.argtypes = [dp, dp, C.c_int, dp]
+        L.orc_map_peak.argtypes = [dp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double)]
+        L.orc_gauss3.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.orc_gauss3.restype = C.c_double
+        L.orc_mw_levels.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, ip, C.POINTER(C.c_int)]
+        L.orc_mw_levels.restype = C.c_int
+        L.orc_mad_filter.argtypes = [ip, ip, C.c_void_p, C.c_int, C.c_int, C.c_double, u8p]
+        L.orc_mad_filter.restype = C.c_long
+        L.orc_multiwindow.argtypes = [dp, dp, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int,
+                                      C.c_double, dp, dp, ip, dp, ip]
+        L.orc_multiwindow.restype = C.c_int
         _lib = L
     return _lib
 
@@ -186,3 +201,81 @@ def correlate(ref, deformed, roi=None, *, subset_size, step, shape=6, tol=1e-4, 
         raise ValueError("no seed could be placed on an active node")
     return dict(p=p, zncc=z, iters=it, status=st, wave=wv, seed_nodes=so[:ns], nx=nx, ny=ny, seconds=dt,
                 u=p[0], v=p[1], subset_size=N, step=step)
+
+
+# ---- multi-window FFT initial guess (mw_oracle.c) ----------------------------
+def fft2(a, inverse=False):
+    """2-D radix-2 FFT of a square complex array (no 1/n scale on the inverse)."""
+    a = np.asarray(a, np.complex128)
+    W = a.shape[0]
+    re = np.ascontiguousarray(a.real)
+    im = np.ascontiguousarray(a.imag)
+    lib().orc_fft2(re, im, W, 1 if inverse else -1)
+    return re + 1j * im
+
+
+def phase_corr(f, g):
+    """Eq. (1) correlation map of two square real windows (scaled by 1/W^2)."""
+    f = _f64(f)
+    r = np.empty_like(f)
+    lib().orc_phase_corr(f, _f64(g), f.shape[0], r)
+    return r
+
+
+def map_peak(r):
+    """Signed peak index (qx, qy) in [-W/2, W/2) and its lead over the next value."""
+    r = _f64(r)
+    qx, qy, m = C.c_int(), C.c_int(), C.c_double()
+    lib().orc_map_peak(r, r.shape[0], C.byref(qx), C.byref(qy), C.byref(m))
+    return qx.value, qy.value, m.value
+
+
+def gauss3(a, b, c):
+    return float(lib().orc_gauss3(float(a), float(b), float(c)))
+
+
+def mw_levels(max_disp, N, W, H):
+    """(regular window sizes, node-level size) of the multi-window schedule."""
+    sizes = np.zeros(32, np.int32)
+    wf = C.c_int()
+    n = lib().orc_mw_levels(int(max_disp), int(N), int(W), int(H), sizes, C.byref(wf))
+    return [int(x) for x in sizes[:n]], wf.value
+
+
+def mad_filter(u, v, ok=None, thr=2.0):
+    """One MAD outlier pass over integer grid fields; returns (u, v, replaced)."""
+    u = np.ascontiguousarray(u, np.int32).copy()
+    v = np.ascontiguousarray(v, np.int32).copy()
+    ny, nx = u.shape
+    rep = np.zeros((ny, nx), np.uint8)
+    okp = None
+    if ok is not None:
+        oka = np.ascontiguousarray(ok, np.uint8)
+        okp = oka.ctypes.data
+    lib().orc_mad_filter(u.reshape(-1), v.reshape(-1), okp, nx, ny, float(thr), rep.reshape(-1))
+    return u, v, rep.astype(bool)
+
+
+def multiwindow(ref, deformed, roi=None, *, subset_size, step, max_disp, subpixel=False, mad_threshold=2.0):
+    """Multi-window FFT estimate at every node: dict of u, v, valid, margin [ny][nx] and the level sizes."""
+    ref = _f64(ref)
+    de = _f64(deformed)
+    H, W = ref.shape
+    N = subset_size
+    nx = (W - N) // step + 1 if W >= N else 0
+    ny = (H - N) // step + 1 if H >= N else 0
+    u = np.zeros((ny, nx))
+    v = np.zeros((ny, nx))
+    val = np.zeros((ny, nx), np.int32)
+    mg = np.zeros((ny, nx))
+    lv = np.zeros(33, np.int32)
+    roi_arr = None
+    roi_ptr = None
+    if roi is not None:
+        roi_arr = np.ascontiguousarray(roi, dtype=np.uint8)
+        roi_ptr = roi_arr.ctypes.data
+    n = lib().orc_multiwindow(ref, de, W, H, roi_ptr, N, step, int(max_disp), int(bool(subpixel)),
+                              float(mad_threshold), u.reshape(-1), v.reshape(-1), val.reshape(-1), mg.reshape(-1), lv)
+    if n < 0:
+        raise ValueError("the image cannot hold a node-level window")
+    return dict(u=u, v=v, valid=val.astype(bool), margin=mg, levels=[int(x) for x in lv[:n]])
