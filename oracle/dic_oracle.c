@@ -402,11 +402,16 @@ static double dp_norm(const double *dp, int np, double h)
  *
  * Levenberg-Marquardt (Sec. 2.2 names it as the optimiser; Gauss-Newton is
  * its zero-damping case), with lambda > 0: the increment solves
- * (H + lambda diag(H)) dp = -b.  Iteration 1 accepts its evaluation; a later
- * evaluation whose cost is not above the last accepted one is accepted and
- * divides lambda by 10, otherwise it is rejected: lambda is multiplied by 10
- * and the step is recomputed from the last accepted p and b.  The convergence
- * test is the same; the ZNCC reported is the last accepted one.
+ * (H + lambda diag(H)) dp = -b, and lambda adapts by Marquardt's rule: an
+ * evaluation that improves on the last accepted one is accepted and divides
+ * lambda by 10; one that does not is rejected: lambda is multiplied by 10 and
+ * the step is retaken from the last accepted p and b.  Reading of "improves":
+ * the merit is the convergence norm of the undamped Gauss-Newton increment at
+ * the evaluated p, zero exactly at the inverse-compositional fixed point.  (The
+ * cost itself is not used: that fixed point is not exactly the cost's
+ * minimiser, and a cost test makes the iteration cycle between the two points
+ * near convergence.)  An accepted evaluation whose merit is below tol takes the
+ * undamped step and is CONVERGED; the ZNCC reported is the last accepted one.
  */
 void orc_icgn_node(const orc_problem *P, double xc, double yc, const double *p_init, orc_node_result *res)
 {
@@ -420,6 +425,7 @@ void orc_icgn_node(const orc_problem *P, double xc, double yc, const double *p_i
     double Hm[NPMAX * NPMAX], L[NPMAX * NPMAX], Ld[NPMAX * NPMAX];
     double p[NPMAX], p_acc[NPMAX], b_acc[NPMAX];
     double lam = P->lm_lambda, best = 0.0, z_acc = 0.0;
+    int damped = 0; /* this iteration takes the damped step */
     memset(p, 0, sizeof(p));
     for (int j = 0; j < np; ++j) p[j] = p_init[j];
     res->zncc = 0.0;
@@ -535,25 +541,40 @@ void orc_icgn_node(const orc_problem *P, double xc, double yc, const double *p_i
         }
         double znssd = rr / (df * df);
         res->zncc = 1.0 - 0.5 * znssd;
+        double y[NPMAX], dp[NPMAX];
         if (lam > 0.0) {
-            const double cval = P->cost == COST_ZNSSD ? znssd : (P->cost == COST_NSSD ? cr / ff : cr);
-            if (it == 1 || cval <= best) {
+            /* merit: the undamped increment's convergence norm at this p */
+            double gd[NPMAX];
+            memset(gd, 0, sizeof(gd));
+            for (int j = 0; j < np; ++j) {
+                double s = b[j];
+                for (int k = 0; k < j; ++k) s -= L[j * np + k] * y[k];
+                y[j] = s / L[j * np + j];
+            }
+            for (int j = np - 1; j >= 0; --j) {
+                double s = y[j];
+                for (int k = j + 1; k < np; ++k) s -= L[k * np + j] * gd[k];
+                gd[j] = s / L[j * np + j];
+            }
+            const double merit = dp_norm(gd, np, h);
+            if (it == 1 || merit <= best) {
                 if (it > 1) lam *= 0.1;
-                best = cval;
+                best = merit;
                 z_acc = res->zncc;
                 memcpy(p_acc, p, sizeof(p));
                 memcpy(b_acc, b, sizeof(b));
+                damped = !(merit < P->tol);
             } else {
                 lam *= 10.0;
                 res->zncc = z_acc;
                 memcpy(p, p_acc, sizeof(p));
                 memcpy(b, b_acc, sizeof(b));
+                damped = 1;
             }
         }
-        double y[NPMAX], dp[NPMAX];
         memset(dp, 0, sizeof(dp));
         const double *Ls = L;
-        if (lam > 0.0) {
+        if (damped) {
             /* Cholesky of H + lambda diag(H) */
             for (int j = 0; j < np; ++j) {
                 double d = Hm[j * np + j] * (1.0 + lam);
@@ -588,7 +609,7 @@ void orc_icgn_node(const orc_problem *P, double xc, double yc, const double *p_i
         int bad = isnan(res->zncc);
         for (int j = 0; j < np; ++j) bad |= isnan(p[j]) || isnan(dp[j]);
         if (bad) { res->status = ST_NAN; goto done; }
-        if (dp_norm(dp, np, h) < P->tol) {
+        if (!damped && dp_norm(dp, np, h) < P->tol) {
             res->status = res->zncc >= P->zncc_min ? ST_CONVERGED : ST_LOW_ZNCC;
             goto done;
         }
