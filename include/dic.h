@@ -44,7 +44,7 @@ typedef enum {
     DIC_E_DEVICE = -3,      /* HIP runtime or kernel error */
     DIC_E_STATE = -4,       /* dic_correlate before dic_set_reference */
     DIC_E_NOSEED = -5,      /* no seed lies on an active node */
-    DIC_E_UNSUPPORTED = -6  /* valid but not built (e.g. rigid shape) */
+    DIC_E_UNSUPPORTED = -6  /* valid but not built (e.g. a variant in the serving loop) */
 } dic_status;
 
 typedef enum { DIC_PIX_U8 = 0, DIC_PIX_U16 = 1, DIC_PIX_F32 = 2 } dic_pixel;
@@ -79,7 +79,7 @@ typedef struct {
 typedef struct {
     int32_t subset_size;        /* N: odd, 5 <= N <= 63 */
     int32_t step;               /* grid step in pixels, >= 1 */
-    int32_t shape;              /* DIC_SHAPE_AFFINE or DIC_SHAPE_QUADRATIC */
+    int32_t shape;              /* dic_shape: rigid, affine or quadratic (Eq. (5)) */
     int32_t max_iter;           /* >= 1 */
     double tol;                 /* convergence threshold on |dp| in pixels (see dic_correlate) */
     double zncc_min;            /* a converged subset with lower ZNCC is LOW_ZNCC and does not propagate */
@@ -95,7 +95,27 @@ typedef struct {
                                    0 = automatic (N + 9: the taps' reach and 3 samples of drift
                                    room on each side), else
                                    N + 5 .. 96; a warped subset that does not fit reads global memory */
+    int32_t cost;               /* dic_cost: the criterion each subset minimises (Sec. 2.2) */
+    double lm_lambda;           /* 0: Gauss-Newton increments; > 0: Levenberg-Marquardt with this initial
+                                   damping: (H + lambda diag H) dp = -b; an evaluation whose undamped
+                                   increment is not longer (convergence norm) than at the last accepted one is
+                                   accepted and divides lambda by 10, else lambda * 10 and the step is retaken
+                                   from the last accepted p; an accepted evaluation with an undamped increment
+                                   below tol takes it and converges; the reported ZNCC is the last accepted */
 } dic_params;
+
+/* Costs of Sec. 2.2.  Every cost reports the ZNCC (1 - ZNSSD/2) as its
+ * correlation coefficient, which also ranks the propagation and is compared
+ * with zncc_min; the seed search is an integer ZNCC search for every cost.
+ * The rigid shape, NSSD, SSD and lm_lambda > 0 run on a general kernel (one
+ * 256-thread workgroup per subset, FP64 sums; threads_per_subset must be 0 or
+ * 256, tile_side and reduce_fp64 are ignored); ZNSSD with the affine or
+ * quadratic shape and lm_lambda = 0 runs on the tuned kernels. */
+typedef enum {
+    DIC_COST_ZNSSD = 0, /* Eq. (4): zero-normalised SSD, residual fbar - (|fbar|/|gbar|) gbar */
+    DIC_COST_NSSD = 1,  /* Eq. (3): normalised SSD, residual f - (|f|/|g|) g */
+    DIC_COST_SSD = 2    /* Eq. (2): residual f - g */
+} dic_cost;
 
 /* A seed: a point near which propagation starts (snapped to the nearest
  * active node) and a guess (u0, v0) for the centre of its integer search. */
@@ -202,6 +222,126 @@ dic_status dic_destroy(dic_ctx *c);
 
 /* Message of the last error on this context ("" if none); valid until the next call. */
 const char *dic_last_error(const dic_ctx *c);
+
+/* ------------------------------------------------------------------------
+ * Multi-window FFT initial guess (Sec. 2.2, Eq. (1); Sec. 4's MAD outlier
+ * removal).
+ *
+ * Rigid displacements from the normalised (phase) cross-correlation of square
+ * windows: powers of two from the smallest above max_disp (at most 4096, and
+ * no larger than the image) down to the smallest power of two holding the
+ * subset (Wf), then one Wf window per node of the reference's grid.  Windows
+ * of a level overlap by half; each is compared with the deformed window
+ * shifted by its integer guess (the exact bilinear interpolation of the
+ * previous level's integer field at its centre, zero on the first level; a
+ * shifted window leaving the image keeps its guess); both are tapered by a
+ * separable Hann weight before the transform.  After every level a 3x3
+ * normalised-median test replaces a window whose u or v differs from its
+ * neighbours' median by more than mad_threshold * (MAD + 1 px) with the
+ * neighbours' medians.  A level resolves shifts up to half its window, so
+ * max_disp should be about twice the largest expected displacement.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t max_disp;      /* estimate of the largest displacement in pixels, >= 1 */
+    int32_t subpixel;      /* 1: 3-point Gaussian fit around each node's peak (the MULTIWINDOW mode) */
+    double mad_threshold;  /* normalised-median threshold (2 is usual); 0 disables the test */
+} dic_mw_params;
+
+/*
+ * The multi-window estimate at every node of the current reference's grid
+ * against `def` (DEVICE image, same size).  Outputs (caller-allocated DEVICE
+ * [ny][nx]): u_out, v_out (integers unless subpixel), valid_out (int8: 1 for
+ * active nodes, 0 elsewhere).  levels_out (HOST, 32 entries, may be NULL):
+ * the window sizes used, the node level last; *nlevels (may be NULL) their
+ * count.  Workspace is kept by the context (two 128 MiB batch buffers and a
+ * few bytes per window).  Returns after completion.
+ */
+dic_status dic_multiwindow(dic_ctx *c, const dic_image *def, const dic_mw_params *prm, float *u_out, float *v_out,
+                           int8_t *valid_out, int32_t *levels_out, int32_t *nlevels);
+
+/* Reliability-guided correlation seeded by the multi-window estimate (the
+ * paper's default MULTIWINDOW_RG): each seed's (u0, v0) becomes the estimate
+ * at the node it snaps to, then dic_correlate runs with those seeds. */
+dic_status dic_correlate_mw(dic_ctx *c, const dic_image *def, const dic_seed *seeds, int32_t nseeds,
+                            const dic_mw_params *prm, dic_result *out);
+
+/* ------------------------------------------------------------------------
+ * Sequences with reference updating (Sec. 6: the reference moves through the
+ * sequence of deformed images to follow large strains).
+ *
+ * Frames are correlated in order against the current reference, which starts
+ * as the context's.  When the fraction of active nodes that converge, or their
+ * mean ZNCC, falls below its threshold (and the previous frame is not already
+ * the reference), the previous frame becomes the reference (dic_set_reference
+ * on it with the same ROI mask and parameters: the context keeps it after the
+ * call) and the frame is correlated again.  Every result is on the original
+ * reference's nodes: node X sits at x = X + u_r(X) in the current reference
+ * (u_r the reference's accumulated result), the incremental result is
+ * interpolated bilinearly at x (terms of non-zero weight only),
+ * u = u_r + u_inc(x), the gradients compose as G = G_inc + G_r + G_inc G_r,
+ * ZNCC interpolates, iterations and wave index come from the nearest node;
+ * status NOT_REACHED where the reference's node did not converge or x leaves
+ * the grid, else the first non-converged status of the weighted nodes.
+ * Seeds: the given positions; the guess is (u0, v0) for frame 0, zero for the
+ * first frame after an update, else the previous frame's incremental result at
+ * the seed's node.  Rigid and affine shapes when updating.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t update;        /* 1: update the reference on a quality drop; 0: every frame against the original */
+    double min_converged;  /* fraction of active nodes that must converge (e.g. 0.95) */
+    double min_zncc;       /* mean ZNCC over converged nodes required (e.g. 0.9) */
+} dic_seq_params;
+
+/* frames: nframes DEVICE images (kept valid during the call); roi_mask_dev as
+ * for dic_set_reference (used for updated references); outs: nframes
+ * caller-allocated results; ref_of_frame (HOST, may be NULL): the frame each
+ * result was correlated against (-1: the original reference). */
+dic_status dic_correlate_sequence(dic_ctx *c, const dic_image *frames, int32_t nframes, const uint8_t *roi_mask_dev,
+                                  const dic_seed *seeds, int32_t nseeds, const dic_seq_params *sp, dic_result *outs,
+                                  int32_t *ref_of_frame);
+
+/* ------------------------------------------------------------------------
+ * Out-of-core correlation (Sec. 6: images split into chunks that are loaded
+ * one at a time, for pairs larger than the device's memory).
+ *
+ * Both images and every output stay in HOST memory; only one band of the pair
+ * is on the device at a time.  The node grid (the one dic_set_reference would
+ * build for the whole image) is cut into bands of band_rows node rows.  A
+ * band's window holds its subsets' pixel rows plus `halo` rows above and
+ * below (the top rounded down to a multiple of the step), with the ROI
+ * limited to the band's subsets; the window becomes the context's reference
+ * (the context keeps the last band's afterwards) and the deformed window is
+ * correlated against it.  Bands are done outward from the band of the first
+ * seed: first downward, then upward.  A band's seeds are the given seeds whose
+ * nearest node row lies in it and, except for the first band, up to
+ * boundary_seeds evenly spaced nodes of its node row next to the finished
+ * neighbour whose node across the boundary converged, guessed with that
+ * node's displacement.  A second sweep, from the outermost bands back toward
+ * the first, correlates again every band that has no converged node, seeded
+ * across its other boundary.  Active nodes of a band with no usable seed stay
+ * NOT_REACHED.  Propagation restarts in every band, so wave indices count from
+ * each band's seeds and a node's starting guess can differ from a single pass
+ * over the whole grid: converged values agree with it within the convergence
+ * threshold where the halo covers the vertical motion (otherwise warped
+ * pixels leave the window and the node is OUT_OF_BOUNDS); the spline
+ * prefilter sees the window's edges, whose influence decays by 0.268 per
+ * pixel.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t band_rows;      /* node rows per band, >= 1 */
+    int32_t halo;           /* extra pixel rows above and below a band, >= 0 (cover |v| plus the spline's reach) */
+    int32_t boundary_seeds; /* seeds taken across each band boundary, 1..64 */
+} dic_chunk_params;
+
+/* ref_host, def_host: HOST images (pitch_bytes in host memory); roi_host: HOST
+ * mask [height][width] or NULL; seeds as for dic_correlate in full-image
+ * pixels; out_host: HOST arrays laid out as dic_result for the whole grid.
+ * Allocates device windows for the tallest band for the duration of the call.
+ * DIC_E_INVAL for bad sizes or parameters; errors of dic_set_reference and
+ * dic_correlate pass through (the outputs then hold the bands done so far). */
+dic_status dic_correlate_chunked(dic_ctx *c, const dic_image *ref_host, const dic_image *def_host,
+                                 const uint8_t *roi_host, const dic_params *prm, const dic_seed *seeds,
+                                 int32_t nseeds, const dic_chunk_params *cp, dic_result *out_host);
 
 /* ------------------------------------------------------------------------
  * Strain post-processing (Sec. 2.3, Eq. (6)-(9)).

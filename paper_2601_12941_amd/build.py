@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdicmi.so")
-SOURCES = ["dic_kernels.hip", "dic_engine.hip", "dic_server.hip", "dic_strain.hip", "dic_noalloc.hip"]
+SOURCES = ["dic_kernels.hip", "dic_engine.hip", "dic_server.hip", "dic_strain.hip", "dic_variants.hip", "dic_fft.hip", "dic_sequence.hip", "dic_chunked.hip", "dic_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("DIC_OFFLOAD_ARCH", "gfx950")
 

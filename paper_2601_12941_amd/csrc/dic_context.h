@@ -28,6 +28,9 @@ inline size_t pixel_size(int pixel) { return pixel == DIC_PIX_U8 ? 1 : (pixel ==
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
+// Multi-window window schedule (dic_fft.hip): regular sizes, node-level size.
+int mw_levels(int max_disp, int N, int W, int H, int *sizes, int *wf);
+
 // Device address of the allocation-free entry point's scratch array on
 // `device` (dic_noalloc.hip); nullptr if the lookup fails.
 void *noalloc_scratch(int device);
@@ -64,6 +67,7 @@ struct dic_ctx {
     bool has_ref = false;
     dic_params prm{};
     int W = 0, H = 0, nx = 0, ny = 0, np = 6, tps = 64;
+    bool variant = false;          // rigid shape, NSSD / SSD or LM damping: the general wave kernel
     int64_t nodes = 0, active = 0;
     int ref_pixel = 0;
 
@@ -91,6 +95,15 @@ struct dic_ctx {
     void *noalloc_base = nullptr;           // this device's scratch array (dic_correlate_noalloc)
     int32_t *h_noalloc = nullptr;           // pinned staging of dic_correlate_noalloc (seeds, frame record)
     double *d_strain_w = nullptr;           // least-squares derivative weights of dic_strain
+    void *mw_a = nullptr, *mw_b = nullptr;  // dic_multiwindow: batch buffers (complex FP32)
+    size_t mw_cap_f2 = 0;
+    void *mw_int = nullptr;                 // dic_multiwindow: per-window integer fields, flags, estimates
+    int64_t mw_cap_w = 0;
+    float *mw_node_u = nullptr;             // dic_correlate_mw: the node estimates
+    int64_t mw_node_cap = 0;
+    void *seq_buf = nullptr;                // dic_correlate_sequence: two incremental results
+    size_t seq_cap = 0;
+    double *seq_part = nullptr;             // dic_correlate_sequence: quality partial sums
     hipEvent_t ev[4] = {};
     std::vector<hipEvent_t> chunk_ev;
     dic_stats stats{};
@@ -124,6 +137,8 @@ struct dic_ctx {
         R.guess_copy = prm.guess_mode;
         R.half = prm.coef_fp16 != 0;
         R.ts = window_side();
+        R.cost = prm.cost;
+        R.lm_lambda = prm.lm_lambda;
         return R;
     }
 };

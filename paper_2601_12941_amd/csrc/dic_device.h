@@ -262,4 +262,40 @@ __device__ __forceinline__ void compose_quadratic(double (&p)[12], const double 
     p[9] = y[0]; p[10] = y[1]; p[11] = y[2];
 }
 
+// Propagation from a CONVERGED node (ix, iy) of wave k, run by one wavefront
+// (lane t of it): lane d < 4 visits the neighbour in direction d (right, left,
+// below, above) if it is active; the first visitor claims it for wave k + 1
+// and appends it to the next frontier list `lout`, and every visitor of this
+// wave raises the child's parent key to (ordered ZNCC << 2 | priority), where
+// the priority 3, 2, 1, 0 says that the child sees this node on its left,
+// right, above or below: the exact-tie order of the parent rule.
+__device__ __forceinline__ void push_children(const FrameState &F, const RefView &R, int ix, int iy, int k,
+                                              float zncc, int32_t *lout, int t)
+{
+    int64_t m = -1;
+    bool inserted = false;
+    if (t < 4) {
+        const int cx = ix + (t == 0 ? 1 : (t == 1 ? -1 : 0));
+        const int cy = iy + (t == 2 ? 1 : (t == 3 ? -1 : 0));
+        if (cx >= 0 && cy >= 0 && cx < R.nx && cy < R.ny) {
+            m = static_cast<int64_t>(cy) * R.nx + cx;
+            if (R.flag[m] >= 0) {
+                const int old = atomicCAS(F.wave + m, -1, k + 1);
+                inserted = old == -1;
+                if (old == -1 || old == k + 1)
+                    atomicMax(reinterpret_cast<unsigned long long *>(F.pkey + m),
+                              static_cast<unsigned long long>((static_cast<uint64_t>(ordered_bits(zncc)) << 2) |
+                                                              (3u - t)));
+            }
+        }
+    }
+    const uint64_t bal = __ballot(inserted);
+    if (bal != 0) {
+        int base = 0;
+        if (t == 0) base = atomicAdd(F.counts + k + 1, __popcll(bal));
+        base = __shfl(base, 0);
+        if (inserted) lout[base + __popcll(bal & ((1ull << t) - 1))] = static_cast<int32_t>(m);
+    }
+}
+
 } // namespace dicmi

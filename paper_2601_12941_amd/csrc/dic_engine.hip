@@ -62,6 +62,12 @@ dic_status dic_destroy(dic_ctx *c)
     dfree(c->d_centre);
     dfree(c->d_zbuf);
     dfree(c->d_strain_w);
+    dfree(c->mw_a);
+    dfree(c->mw_b);
+    dfree(c->mw_int);
+    dfree(c->mw_node_u);
+    dfree(c->seq_buf);
+    dfree(c->seq_part);
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
     if (c->h_stats) (void)hipHostFree(c->h_stats);
     if (c->h_noalloc) (void)hipHostFree(c->h_noalloc);
@@ -103,8 +109,11 @@ dic_status dic_set_reference(dic_ctx *c, const dic_image *ref, const uint8_t *ro
     if (p.subset_size < 5 || p.subset_size > 63 || (p.subset_size & 1) == 0)
         FAIL(DIC_E_INVAL, "subset_size %d (odd, 5..63)", p.subset_size);
     if (p.step < 1) FAIL(DIC_E_INVAL, "step %d", p.step);
-    if (p.shape == DIC_SHAPE_RIGID) FAIL(DIC_E_UNSUPPORTED, "rigid shape function is not built");
-    if (p.shape != DIC_SHAPE_AFFINE && p.shape != DIC_SHAPE_QUADRATIC) FAIL(DIC_E_INVAL, "shape %d", p.shape);
+    if (p.shape != DIC_SHAPE_RIGID && p.shape != DIC_SHAPE_AFFINE && p.shape != DIC_SHAPE_QUADRATIC)
+        FAIL(DIC_E_INVAL, "shape %d", p.shape);
+    if (p.cost < DIC_COST_ZNSSD || p.cost > DIC_COST_SSD) FAIL(DIC_E_INVAL, "cost %d", p.cost);
+    if (!(p.lm_lambda >= 0.0) || !std::isfinite(p.lm_lambda)) FAIL(DIC_E_INVAL, "lm_lambda %g", p.lm_lambda);
+    const bool variant = p.shape == DIC_SHAPE_RIGID || p.cost != DIC_COST_ZNSSD || p.lm_lambda > 0.0;
     if (p.max_iter < 1 || p.max_iter > 32767) FAIL(DIC_E_INVAL, "max_iter %d", p.max_iter);
     if (!(p.tol > 0.0) || !std::isfinite(p.tol)) FAIL(DIC_E_INVAL, "tol %g", p.tol);
     if (!std::isfinite(p.zncc_min)) FAIL(DIC_E_INVAL, "zncc_min %g", p.zncc_min);
@@ -113,14 +122,16 @@ dic_status dic_set_reference(dic_ctx *c, const dic_image *ref, const uint8_t *ro
     if (ref->width < p.subset_size || ref->height < p.subset_size)
         FAIL(DIC_E_INVAL, "image %dx%d smaller than subset %d", ref->width, ref->height, p.subset_size);
     int tps = p.threads_per_subset;
-    if (tps == 0) tps = p.subset_size <= 23 ? 64 : (p.subset_size <= 37 ? 128 : 256);
-    if (!supported_tps(p.subset_size, tps))
+    if (tps == 0) tps = variant ? 256 : (p.subset_size <= 23 ? 64 : (p.subset_size <= 37 ? 128 : 256));
+    if (variant && tps != 256)
+        FAIL(DIC_E_INVAL, "threads_per_subset %d: the rigid shape, NSSD, SSD and LM run 256 threads per subset", tps);
+    if (!variant && !supported_tps(p.subset_size, tps))
         FAIL(DIC_E_INVAL, "threads_per_subset %d unsupported for subset %d", tps, p.subset_size);
     if (p.tile_side != 0 && (p.tile_side < p.subset_size + 5 || p.tile_side > 96))
         FAIL(DIC_E_INVAL, "tile_side %d (0, or %d..96)", p.tile_side, p.subset_size + 5);
     if (tps < 64 && p.shape != DIC_SHAPE_AFFINE)
         FAIL(DIC_E_UNSUPPORTED, "packed subsets (%d threads per subset) are built for the affine shape", tps);
-    if (p.shape == DIC_SHAPE_QUADRATIC && tps == 64 && p.subset_size > 21)
+    if (!variant && p.shape == DIC_SHAPE_QUADRATIC && tps == 64 && p.subset_size > 21)
         FAIL(DIC_E_UNSUPPORTED, "quadratic shape with 64 threads is built for subsets up to 21");
 
     HIPCHK(hipSetDevice(c->device));
@@ -130,6 +141,7 @@ dic_status dic_set_reference(dic_ctx *c, const dic_image *ref, const uint8_t *ro
     c->prm.threads_per_subset = tps;
     c->tps = tps;
     c->np = p.shape;
+    c->variant = variant;
     c->W = ref->width;
     c->H = ref->height;
     c->nx = (c->W - p.subset_size) / p.step + 1;
@@ -146,13 +158,14 @@ dic_status dic_set_reference(dic_ctx *c, const dic_image *ref, const uint8_t *ro
     HIPCHK(hipMalloc(&c->pf, sizeof(float) * c->ppitch * c->H));
     HIPCHK(hipMalloc(&c->pfx, sizeof(float) * c->ppitch * c->H));
     HIPCHK(hipMalloc(&c->pfy, sizeof(float) * c->ppitch * c->H));
-    HIPCHK(hipMalloc(&c->cache, sizeof(double) * cache_slots(c->np) * c->nodes));
+    // the general kernel of the variants reduces the reference side per subset: no per-node cache
+    if (!variant) HIPCHK(hipMalloc(&c->cache, sizeof(double) * cache_slots(c->np) * c->nodes));
     HIPCHK(hipMalloc(&c->flag, c->nodes));
     const size_t rowb = c->W * pixel_size(ref->pixel);
     HIPCHK(hipMalloc(&c->ref_raw, rowb * c->H));
     HIPCHK(hipMalloc(&c->d_wave_total, sizeof(int32_t) * (c->nodes + 130)));
     HIPCHK(hipMemcpy2DAsync(c->ref_raw, rowb, ref->data, ref->pitch_bytes, rowb, c->H, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemsetAsync(c->cache, 0, sizeof(double) * cache_slots(c->np) * c->nodes, s));
+    if (!variant) HIPCHK(hipMemsetAsync(c->cache, 0, sizeof(double) * cache_slots(c->np) * c->nodes, s));
 
     RefView R = c->view();
     HIPCHK(hipMalloc(&c->d_view, sizeof(RefView)));
@@ -161,7 +174,7 @@ dic_status dic_set_reference(dic_ctx *c, const dic_image *ref, const uint8_t *ro
                      c->cpitch, false, s);
     launch_ref_pixels(R, c->pf, c->pfx, c->pfy, s);
     launch_active(roi_mask_dev, R, c->flag, s);
-    if (!launch_ref_nodes(R, c->np, tps, c->cache, c->flag, s)) {
+    if (!variant && !launch_ref_nodes(R, c->np, tps, c->cache, c->flag, s)) {
         HIPCHK(hipStreamSynchronize(s));
         free_reference(c);
         FAIL(DIC_E_UNSUPPORTED, "no reference-precompute kernel for shape %d, %d threads, subset %d", c->np, tps,
@@ -284,7 +297,7 @@ dic_status run_frames(dic_ctx *c, const dic_image *defs, int nframes, int nseeds
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(c->ev[2], s));
 
-    const int grid = wave_grid_hint(c->np, c->tps, c->device);
+    const int grid = c->variant ? wave_grid_hint(c->np, 256, c->device) : wave_grid_hint(c->np, c->tps, c->device);
     FrameTable table;
     std::memset(&table, 0, sizeof(table));
     for (int f = 0; f < nframes; ++f) table.f[f] = hf[f];
@@ -303,7 +316,8 @@ dic_status run_frames(dic_ctx *c, const dic_image *defs, int nframes, int nseeds
             HIPCHK(hipEventRecord(c->chunk_ev[2 * nchunk], s));
         }
         for (int j = 0; j < chunk && k <= c->nodes; ++j, ++k)
-            if (!launch_wave(table, k, c->np, c->prm.subset_size, c->tps, f64, R.ts, grid, s))
+            if (c->variant ? !launch_wave_var(table, k, c->np, grid, s)
+                           : !launch_wave(table, k, c->np, c->prm.subset_size, c->tps, f64, R.ts, grid, s))
                 FAIL(DIC_E_UNSUPPORTED, "no kernel for shape %d, %d threads, subset %d", c->np, c->tps,
                      c->prm.subset_size);
         HIPCHK(hipGetLastError());

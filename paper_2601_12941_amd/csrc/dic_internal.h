@@ -57,6 +57,8 @@ struct RefView {
     int guess_copy;      // 1: copy the neighbour's p, 0: extrapolate
     int half;            // deformed coefficients stored as FP16
     int ts;              // side of the LDS coefficient window
+    int cost;            // 0 ZNSSD (Eq. (4)), 1 NSSD (Eq. (3)), 2 SSD (Eq. (2)); the variant kernel only
+    double lm_lambda;    // initial Levenberg-Marquardt damping (0: Gauss-Newton); the variant kernel only
 };
 
 // Device-resident state of one frame of a (batched) correlation.
@@ -111,6 +113,8 @@ int pixels_per_thread(int N, int T);
 void launch_finalize(const RefView &R, const FrameState &F, int np, bool nan_unconverged, hipStream_t s);
 int wave_grid_hint(int np, int tps, int device);
 bool supported_tps(int N, int tps);
+// the variants' wave kernel (rigid shape, NSSD / SSD, Levenberg-Marquardt; dic_variants.hip)
+bool launch_wave_var(const FrameTable &F, int step, int np, int grid, hipStream_t s);
 int tile_side(int N);
 
 } // namespace dicmi

@@ -1288,35 +1288,7 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
             F.iters[node] = static_cast<int16_t>(iters);
             F.status[node] = static_cast<int8_t>(status);
         }
-        if (status == kConverged && t < 64) {
-            // lane d (< 4) visits the neighbour in direction d: right, left, below,
-            // above.  That child sees this node as its left (3), right (2), upper
-            // (1) or lower (0) neighbour: the tie-break priority in its parent key.
-            int64_t m = -1;
-            bool inserted = false;
-            if (t < 4) {
-                const int cx = ix + (t == 0 ? 1 : (t == 1 ? -1 : 0));
-                const int cy = iy + (t == 2 ? 1 : (t == 3 ? -1 : 0));
-                if (cx >= 0 && cy >= 0 && cx < R.nx && cy < R.ny) {
-                    m = static_cast<int64_t>(cy) * R.nx + cx;
-                    if (R.flag[m] >= 0) {
-                        const int old = atomicCAS(F.wave + m, -1, k + 1);
-                        inserted = old == -1;
-                        if (old == -1 || old == k + 1)
-                            atomicMax(reinterpret_cast<unsigned long long *>(F.pkey + m),
-                                      static_cast<unsigned long long>(
-                                          (static_cast<uint64_t>(ordered_bits(zncc_out)) << 2) | (3u - t)));
-                    }
-                }
-            }
-            const uint64_t bal = __ballot(inserted);
-            if (bal != 0) {
-                int base = 0;
-                if (t == 0) base = atomicAdd(F.counts + k + 1, __popcll(bal));
-                base = __shfl(base, 0);
-                if (inserted) lout[base + __popcll(bal & ((1ull << t) - 1))] = static_cast<int32_t>(m);
-            }
-        }
+        if (status == kConverged && t < 64) push_children(F, R, ix, iy, k, zncc_out, lout, t);
     }
 }
 

@@ -306,6 +306,8 @@ dic_status dic_server_add_reference(dic_server *s, const dic_image *ref, const u
     if (!s || !ref_id) return DIC_E_INVAL;
     s->err.clear();
     if (!ref || !prm) SFAIL(DIC_E_INVAL, "reference image or params is NULL");
+    if (prm->shape == DIC_SHAPE_RIGID || prm->cost != DIC_COST_ZNSSD || prm->lm_lambda != 0.0)
+        SFAIL(DIC_E_UNSUPPORTED, "the serving loop runs ZNSSD with the affine or quadratic shape and lm_lambda 0");
     if (ref->width >= prm->subset_size && ref->height >= prm->subset_size && prm->step >= 1 &&
         (prm->shape == DIC_SHAPE_AFFINE || prm->shape == DIC_SHAPE_QUADRATIC)) {
         // budget check before anything is allocated; idle pooled scratch goes first

@@ -23,6 +23,7 @@ DIC_OK, DIC_E_INVAL, DIC_E_NOMEM, DIC_E_DEVICE, DIC_E_STATE, DIC_E_NOSEED, DIC_E
 STATUS_NAMES = {0: "OK", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_STATE", -5: "E_NOSEED",
                 -6: "E_UNSUPPORTED"}
 PIX_U8, PIX_U16, PIX_F32 = 0, 1, 2
+COST = {"znssd": 0, "nssd": 1, "ssd": 2}
 SHAPE_RIGID, SHAPE_AFFINE, SHAPE_QUADRATIC = 2, 6, 12
 NODE = dict(CONVERGED=0, NOT_REACHED=1, NOT_IN_ROI=2, MAX_ITER=3, LOW_ZNCC=4, OUT_OF_BOUNDS=5, FLAT_REF=6,
             FLAT_DEF=7, SINGULAR=8, NAN=9)
@@ -30,7 +31,7 @@ NODE = dict(CONVERGED=0, NOT_REACHED=1, NOT_IN_ROI=2, MAX_ITER=3, LOW_ZNCC=4, OU
 # exported names, in the order include/dic.h declares them
 EXPORTS = ["dic_create", "dic_set_reference", "dic_grid_shape", "dic_correlate", "dic_correlate_batch",
            "dic_correlate_noalloc", "dic_noalloc_scratch_bytes", "dic_get_stats", "dic_destroy", "dic_last_error",
-           "dic_strain", "dic_vsg",
+           "dic_multiwindow", "dic_correlate_mw", "dic_correlate_sequence", "dic_correlate_chunked", "dic_strain", "dic_vsg",
            "dic_server_create", "dic_server_add_reference", "dic_server_remove_reference", "dic_server_submit",
            "dic_server_step", "dic_server_poll", "dic_server_forget", "dic_server_get_stats", "dic_server_destroy",
            "dic_server_last_error"]
@@ -45,7 +46,8 @@ class DicParams(C.Structure):
     _fields_ = [("subset_size", C.c_int32), ("step", C.c_int32), ("shape", C.c_int32), ("max_iter", C.c_int32),
                 ("tol", C.c_double), ("zncc_min", C.c_double), ("seed_radius", C.c_int32),
                 ("guess_mode", C.c_int32), ("coef_fp16", C.c_int32), ("reduce_fp64", C.c_int32),
-                ("nan_unconverged", C.c_int32), ("threads_per_subset", C.c_int32), ("tile_side", C.c_int32)]
+                ("nan_unconverged", C.c_int32), ("threads_per_subset", C.c_int32), ("tile_side", C.c_int32),
+                ("cost", C.c_int32), ("lm_lambda", C.c_double)]
 
 
 class DicSeed(C.Structure):
@@ -63,6 +65,18 @@ class DicStats(C.Structure):
                 ("threads_per_subset", C.c_int32), ("seed_du", C.c_int32), ("seed_dv", C.c_int32),
                 ("ms_total", C.c_double), ("ms_icgn", C.c_double), ("ms_prefilter", C.c_double),
                 ("ms_wave_kernels", C.c_double), ("wave_launches", C.c_int32)]
+
+
+class DicMwParams(C.Structure):
+    _fields_ = [("max_disp", C.c_int32), ("subpixel", C.c_int32), ("mad_threshold", C.c_double)]
+
+
+class DicSeqParams(C.Structure):
+    _fields_ = [("update", C.c_int32), ("min_converged", C.c_double), ("min_zncc", C.c_double)]
+
+
+class DicChunkParams(C.Structure):
+    _fields_ = [("band_rows", C.c_int32), ("halo", C.c_int32), ("boundary_seeds", C.c_int32)]
 
 
 class DicStrainParams(C.Structure):
@@ -112,6 +126,13 @@ def load_library(path: str = LIB_PATH):
     L.dic_strain.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
                              P(DicStrainParams), C.c_void_p, C.c_void_p]
     L.dic_vsg.argtypes = [C.c_int32, C.c_int32, C.c_int32]
+    L.dic_multiwindow.argtypes = [C.c_void_p, P(DicImage), P(DicMwParams), C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, P(C.c_int32)]
+    L.dic_correlate_mw.argtypes = [C.c_void_p, P(DicImage), P(DicSeed), C.c_int32, P(DicMwParams), P(DicResult)]
+    L.dic_correlate_sequence.argtypes = [C.c_void_p, P(DicImage), C.c_int32, C.c_void_p, P(DicSeed), C.c_int32,
+                                         P(DicSeqParams), P(DicResult), P(C.c_int32)]
+    L.dic_correlate_chunked.argtypes = [C.c_void_p, P(DicImage), P(DicImage), C.c_void_p, P(DicParams), P(DicSeed),
+                                        C.c_int32, P(DicChunkParams), P(DicResult)]
     L.dic_destroy.argtypes = [C.c_void_p]
     L.dic_last_error.argtypes = [C.c_void_p]
     L.dic_last_error.restype = C.c_char_p
@@ -198,6 +219,39 @@ def dic_strain(ctx, u_ptr: int, v_ptr: int, status_ptr: int, nx: int, ny: int, s
     _check(ctx, load_library().dic_strain(ctx, C.c_void_p(u_ptr), C.c_void_p(v_ptr), C.c_void_p(status_ptr or 0),
                                           int(nx), int(ny), int(step), C.byref(params), C.c_void_p(F_ptr),
                                           C.c_void_p(eps_ptr)))
+
+
+def dic_multiwindow(ctx, image: DicImage, params: DicMwParams, u_ptr: int, v_ptr: int, valid_ptr: int):
+    lv = (C.c_int32 * 32)()
+    n = C.c_int32()
+    _check(ctx, load_library().dic_multiwindow(ctx, C.byref(image), C.byref(params), C.c_void_p(u_ptr),
+                                               C.c_void_p(v_ptr), C.c_void_p(valid_ptr), lv, C.byref(n)))
+    return [lv[i] for i in range(n.value)]
+
+
+def dic_correlate_mw(ctx, image: DicImage, seeds: Sequence[DicSeed], params: DicMwParams, result: DicResult):
+    arr = (DicSeed * len(seeds))(*seeds)
+    _check(ctx, load_library().dic_correlate_mw(ctx, C.byref(image), arr, len(seeds), C.byref(params),
+                                                C.byref(result)))
+
+
+def dic_correlate_sequence(ctx, images: Sequence[DicImage], roi_ptr: int, seeds: Sequence[DicSeed],
+                           params: DicSeqParams, results: Sequence[DicResult]):
+    ims = (DicImage * len(images))(*images)
+    sds = (DicSeed * len(seeds))(*seeds)
+    res = (DicResult * len(results))(*results)
+    refs = (C.c_int32 * len(images))()
+    _check(ctx, load_library().dic_correlate_sequence(ctx, ims, len(images), C.c_void_p(roi_ptr or 0), sds,
+                                                      len(seeds), C.byref(params), res, refs))
+    return list(refs)
+
+
+def dic_correlate_chunked(ctx, ref: DicImage, deformed: DicImage, roi_host_ptr: int, params: DicParams,
+                          seeds: Sequence[DicSeed], chunk: DicChunkParams, result: DicResult):
+    sds = (DicSeed * len(seeds))(*seeds)
+    _check(ctx, load_library().dic_correlate_chunked(ctx, C.byref(ref), C.byref(deformed),
+                                                     C.c_void_p(roi_host_ptr or 0), C.byref(params), sds, len(seeds),
+                                                     C.byref(chunk), C.byref(result)))
 
 
 def dic_vsg(window: int, step: int, subset_size: int) -> int:
@@ -330,10 +384,9 @@ class Engine:
 
     def set_reference(self, ref, roi=None, *, subset_size, step, shape=6, tol=1e-4, max_iter=50, zncc_min=0.7,
                       seed_radius=8, guess="extrapolate", coef_fp16=False, reduce_fp64=True, nan_unconverged=False,
-                      threads_per_subset=0, tile_side=0):
-        prm = DicParams(subset_size, step, shape, max_iter, tol, zncc_min, seed_radius,
-                        1 if guess == "copy" else 0, int(bool(coef_fp16)), int(bool(reduce_fp64)),
-                        int(bool(nan_unconverged)), threads_per_subset, tile_side)
+                      threads_per_subset=0, tile_side=0, cost="znssd", lm_lambda=0.0):
+        prm = _params(subset_size, step, shape, tol, max_iter, zncc_min, seed_radius, guess, coef_fp16, reduce_fp64,
+                      nan_unconverged, threads_per_subset, tile_side, cost, lm_lambda)
         roi_ptr = 0
         if roi is not None:
             import torch
@@ -395,6 +448,69 @@ class Engine:
         dic_correlate_batch(self.ctx, [_image(f) for f in frames], flat, ns, list(ress))
         return list(outs)
 
+    def multiwindow(self, deformed, *, max_disp, subpixel=False, mad_threshold=2.0):
+        """dic_multiwindow: per-node rigid estimates u, v (float32) and valid (int8), plus the level sizes."""
+        import torch
+        nx, ny = self.grid[0], self.grid[1]
+        u = torch.empty((ny, nx), dtype=torch.float32, device=self.device)
+        v = torch.empty_like(u)
+        valid = torch.empty((ny, nx), dtype=torch.int8, device=self.device)
+        lv = dic_multiwindow(self.ctx, _image(deformed), DicMwParams(int(max_disp), int(bool(subpixel)),
+                                                                     float(mad_threshold)),
+                             u.data_ptr(), v.data_ptr(), valid.data_ptr())
+        return {"u": u, "v": v, "valid": valid, "levels": lv}
+
+    def correlate_mw(self, deformed, seeds, *, max_disp, mad_threshold=2.0):
+        """dic_correlate_mw: reliability-guided correlation seeded by the multi-window estimate."""
+        out, res = self._alloc()
+        dic_correlate_mw(self.ctx, _image(deformed), self._seeds(seeds),
+                         DicMwParams(int(max_disp), 0, float(mad_threshold)), res)
+        return out
+
+    def correlate_sequence(self, frames, seeds, roi=None, *, update=True, min_converged=0.95, min_zncc=0.9):
+        """dic_correlate_sequence: every frame on the original nodes, and the reference of each."""
+        outs, ress = zip(*[self._alloc() for _ in frames])
+        refs = dic_correlate_sequence(self.ctx, [_image(f) for f in frames], _roi_ptr(roi, self.ref),
+                                      self._seeds(seeds), DicSeqParams(int(bool(update)), float(min_converged),
+                                                                       float(min_zncc)), list(ress))
+        return list(outs), refs
+
+    def correlate_chunked(self, ref, deformed, roi=None, *, seeds, band_rows, halo, boundary_seeds=8, **params):
+        """dic_correlate_chunked on HOST numpy images (uint8, uint16 or float32
+        [H][W]) and an optional host uint8 ROI: the whole grid's result as host
+        numpy arrays, with one band of the pair on the device at a time.  The
+        context's reference afterwards is the last band's window."""
+        import numpy as np
+        ref = np.ascontiguousarray(ref)
+        deformed = np.ascontiguousarray(deformed)
+        if ref.shape != deformed.shape or ref.dtype != deformed.dtype or ref.ndim != 2:
+            raise ValueError("reference and deformed must be 2-D host arrays of one shape and dtype")
+        pix = {np.dtype(np.uint8): PIX_U8, np.dtype(np.uint16): PIX_U16, np.dtype(np.float32): PIX_F32}.get(ref.dtype)
+        if pix is None:
+            raise ValueError("pixels must be uint8, uint16 or float32")
+        H, W = ref.shape
+        if roi is not None:
+            roi = np.ascontiguousarray(roi, dtype=np.uint8)
+            if roi.shape != ref.shape:
+                raise ValueError("roi must be shaped like the images")
+        shape = params.get("shape", 6)
+        N, st = params["subset_size"], params["step"]
+        if N > min(W, H) or st < 1:
+            raise ValueError("subset larger than the image, or step < 1")
+        nx, ny = (W - N) // st + 1, (H - N) // st + 1
+        out = dict(p=np.empty((shape, ny, nx), np.float32), zncc=np.empty((ny, nx), np.float32),
+                   iters=np.empty((ny, nx), np.int16), status=np.empty((ny, nx), np.int8),
+                   wave=np.empty((ny, nx), np.int32))
+        res = DicResult(*[out[k].ctypes.data for k in ("p", "zncc", "iters", "status", "wave")])
+        ri = DicImage(W, H, ref.strides[0], pix, ref.ctypes.data)
+        di = DicImage(W, H, deformed.strides[0], pix, deformed.ctypes.data)
+        dic_correlate_chunked(self.ctx, ri, di, roi.ctypes.data if roi is not None else 0, _params(**params),
+                              self._seeds(seeds), DicChunkParams(int(band_rows), int(halo), int(boundary_seeds)), res)
+        self.ref = None
+        self.shape = shape
+        self.grid = dic_grid_shape(self.ctx)
+        return out
+
     def strain(self, u, v, status=None, *, step, window=5, basis="bilinear", measure="green_lagrange"):
         """dic_strain on device displacement planes u, v [ny][nx] (e.g. a result's p[0], p[1])."""
         import torch
@@ -417,10 +533,10 @@ class Engine:
 
 def _params(subset_size, step, shape=6, tol=1e-4, max_iter=50, zncc_min=0.7, seed_radius=8, guess="extrapolate",
             coef_fp16=False, reduce_fp64=True, nan_unconverged=False, threads_per_subset=0,
-            tile_side=0) -> DicParams:
+            tile_side=0, cost="znssd", lm_lambda=0.0) -> DicParams:
     return DicParams(subset_size, step, shape, max_iter, tol, zncc_min, seed_radius, 1 if guess == "copy" else 0,
                      int(bool(coef_fp16)), int(bool(reduce_fp64)), int(bool(nan_unconverged)), threads_per_subset,
-                     tile_side)
+                     tile_side, COST[cost], float(lm_lambda))
 
 
 def _roi_ptr(roi, ref) -> int:

@@ -201,6 +201,12 @@ def field_quadratic_c3(W: int, H: int) -> Field:
     return f
 
 
+def field_large(W: int, H: int) -> Field:
+    """A displacement far beyond any subset: translation (0.1526 W, -0.0915 H)
+    (312.6, -187.3 px at 2048^2) plus 1 % / -0.5 % normal strain about the centre."""
+    return field_affine(0.1526 * W, -0.0915 * H, dudx=0.01, dvdy=-0.005, xc=W / 2.0, yc=H / 2.0)
+
+
 def field_bump_c4(W: int, H: int, t=(3.41, -7.92), amp=0.8, width=4000.0) -> Field:
     """(u, v) = (t_x + amp exp(-r^2 / (2 width^2)), t_y), r from the image centre."""
     xc, yc = W / 2.0, H / 2.0
@@ -363,6 +369,7 @@ class Workload:
     seed_noise_ref: int
     seed_noise_def: int
     field_name: str
+    max_disp: int = 0         # multi-window FFT: estimate of the largest displacement (0: not used)
 
     def field(self) -> Field:
         if self.field_name == "c1":
@@ -373,6 +380,8 @@ class Workload:
             return field_quadratic_c3(self.W, self.H)
         if self.field_name == "bump":
             return field_bump_c4(self.W, self.H)
+        if self.field_name == "large":
+            return field_large(self.W, self.H)
         raise ValueError(self.field_name)
 
     def pair(self) -> Pair:
@@ -411,6 +420,14 @@ def workload(name: str, size: Optional[int] = None, **over) -> Workload:
                  amp=(60.0, 200.0), noise=2.0, N=41, step=20, shape=6, tol=1e-4, max_iter=50, zncc_min=0.7,
                  seed_radius=12, seeds=seeds, seed_blobs=4001, seed_noise_ref=4002, seed_noise_def=4003,
                  field_name="bump")
+    elif name == "large":   # 2048^2 u8 speckle, translation of ~0.15 image widths: multi-window FFT seeding
+        W = size or 2048
+        # dense SEM-like speckle (0.03 blobs/px^2, sigma 1.5-3 px): a 32-px window holds enough
+        # texture for its phase-correlation peak
+        d = dict(name="large", W=W, H=W, bits=8, nblobs=int(round(0.03 * W * W)), sigma=(1.5, 3.0),
+                 amp=(60.0, 200.0), noise=2.0, N=31, step=8, shape=6, tol=1e-4, max_iter=50, zncc_min=0.7,
+                 seed_radius=8, seeds=[(W / 2, W / 2, 0.0, 0.0)], seed_blobs=6001, seed_noise_ref=6002,
+                 seed_noise_def=6003, field_name="large", max_disp=int(round(0.3125 * W)))
     else:
         raise ValueError(name)
     d.update(over)

@@ -170,8 +170,14 @@ def test_error_paths():
         eng.set_reference(ref, None, **{**prm, "subset_size": 20})
     assert e.value.code == dic.DIC_E_INVAL
     with pytest.raises(dic.DicError) as e:
-        eng.set_reference(ref, None, **{**prm, "shape": 2})
+        eng.set_reference(ref, None, **{**prm, "shape": 12, "subset_size": 25, "threads_per_subset": 64})
     assert e.value.code == dic.DIC_E_UNSUPPORTED
+    with pytest.raises(dic.DicError) as e:
+        eng.set_reference(ref, None, **{**prm, "shape": 2, "threads_per_subset": 64})
+    assert e.value.code == dic.DIC_E_INVAL
+    with pytest.raises(dic.DicError) as e:
+        eng.set_reference(ref, None, **{**prm, "cost": "ssd", "lm_lambda": -1.0})
+    assert e.value.code == dic.DIC_E_INVAL
     eng.set_reference(ref, torch.from_numpy(pair.roi).cuda(), **prm)
     with pytest.raises(dic.DicError) as e:
         eng.correlate(dic.to_device_image(pair.deformed[:-1]), w.seeds)
