@@ -20,6 +20,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -143,7 +144,7 @@ PMC_BENCH = "bench.py --steps 1 --warmup 0 --latency-runs 1 --cpu-crop 0 " + _SH
 
 
 def _short(name):
-    name = name.replace("dicmi::", "").replace("void ", "")
+    name = name.replace("(anonymous namespace)::", "").replace("dicmi::", "").replace("void ", "")
     return name.split("(")[0]
 
 
@@ -175,6 +176,34 @@ def summarize_trace(d, out):
               "Kernel build at the time of this profile: sha256 `%s` of `paper_2601_12941_amd/csrc/dic_kernels.hip` "
               "and its compile flags (`build.kernel_build_id()`)."
               % kid]
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("wrote", out)
+
+
+def summarize_ext_trace(d, out):
+    """profiles/*.md for the entry points around the path (--workload extensions)
+    from a rocprofv3 --kernel-trace --stats directory: every kernel, calls, time."""
+    import csv
+    stats = next(os.path.join(r, f) for r, _, fs in os.walk(d) for f in fs if f.endswith("kernel_stats.csv"))
+    rows = sorted(csv.DictReader(open(stats)), key=lambda r: -float(r["TotalDurationNs"]))
+    lines = ["# Entry points around the path: rocprofv3 kernel trace of `bench.py --workload extensions`", "",
+             "Command (from the repository root on the MI355X box; rocprofv3 run from /tmp with TMPDIR=/tmp):", "",
+             "```", "rocprofv3 --kernel-trace --stats -f csv -d <out> -o run -- python3 bench.py --workload extensions",
+             "```", "",
+             "Summary written by `python bench.py --summarize-ext-trace <out> --summary-out <this file>`. The run "
+             "correlates: the 2048^2 large-displacement pair (multi-window guess 5 times with the sub-pixel fit, "
+             "then `dic_correlate_mw` 3 times and one plain correlation); the 2048^2 u8 affine pair (ZNSSD "
+             "affine 3 times, strain 10 times for each of two settings, the rigid shape, NSSD, SSD, LM and the "
+             "quadratic shape 3 times each plus one warm-up each, out-of-core twice); the 1024^2 8-frame "
+             "sequence twice. Calls count every launch of the run.", "",
+             "| Kernel | Calls | Total ms | Average us | Min us | Max us |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        if float(r["TotalDurationNs"]) < 1e5:
+            continue
+        lines.append("| `%s` | %s | %.2f | %.1f | %.1f | %.1f |" % (
+            _short(r["Name"]), r["Calls"], float(r["TotalDurationNs"]) / 1e6, float(r["AverageNs"]) / 1e3,
+            float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3))
+    lines += ["", "Kernels under 0.1 ms in total are left out."]
     open(out, "w").write("\n".join(lines) + "\n")
     print("wrote", out)
 
@@ -633,6 +662,198 @@ def serve(args):
     srv.close()
 
 
+def _event_ms(fn, reps):
+    """Median over reps of the device time between events recorded on the
+    current stream (the library's stream) around one call, and the last result."""
+    import torch
+    ts, r = [], None
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        r = fn()
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts)), r
+
+
+def _host_s(fn):
+    t = time.perf_counter()
+    r = fn()
+    return time.perf_counter() - t, r
+
+
+def extensions(args):
+    """The entry points beyond the single-pair path, each timed on MI355X on a
+    workload of the paper's kind, with the oracle timed beside it on a bounded
+    sample (one host thread unless stated): multi-window FFT initial guess and
+    the correlation it seeds, strain, the rigid shape, NSSD/SSD costs and
+    Levenberg-Marquardt, multi-frame correlation with reference updating, and
+    out-of-core (band-by-band) correlation from host memory."""
+    import torch
+    import oracle
+    from oracle import chunked as OCH
+    from oracle import sequence as OSQ
+    from oracle import strain as OST
+    from paper_2601_12941_amd import dic, synth
+    t0 = time.perf_counter()
+    rows = []
+
+    def note(msg):
+        print("# %6.1f s  %s" % (time.perf_counter() - t0, msg), file=sys.stderr, flush=True)
+
+    def emit(rec):
+        rows.append(rec)
+        note(json.dumps(rec))
+
+    eng = dic.Engine(0)
+    # ---- multi-window FFT guess and the correlation it seeds: 2048^2 dense speckle,
+    # translation ~0.15 image widths (far beyond any integer search radius)
+    w = synth.workload("large", size=args.size)
+    pair = w.pair()
+    d_ref, d_def = dic.to_device_image(pair.ref), dic.to_device_image(pair.deformed)
+    d_roi = torch.from_numpy(pair.roi).cuda()
+    eng.set_reference(d_ref, d_roi, **w.params())
+    ms, r = _event_ms(lambda: eng.multiwindow(d_def, max_disp=w.max_disp, subpixel=True), 5)
+    nodes = int(r["valid"].sum().item())
+    wo = synth.workload("large", size=384)
+    po = wo.pair()
+    sec, ro = _host_s(lambda: oracle.multiwindow(po.ref, po.deformed, po.roi, subset_size=wo.N, step=wo.step,
+                                                 max_disp=wo.max_disp, subpixel=True))
+    # algorithmic work: per window pair of side W, 20 W^2 log2 W flop of transforms, its
+    # 2 W^2 pixels, and for windows above 64 samples (HBM batch buffers) 128 W^2 bytes
+    # of complex traffic; level grids: 50 %-overlap tiles of the image, then the nodes
+    nxn, nyn = eng.grid[0], eng.grid[1]
+    flop, nbytes, nwin = 0.0, 0.0, 0
+    for li, Wl in enumerate(r["levels"]):
+        cnt = nxn * nyn if li == len(r["levels"]) - 1 else \
+            ((w.W - Wl) // (Wl // 2) + 1) * ((w.H - Wl) // (Wl // 2) + 1)
+        nwin += cnt
+        flop += cnt * 20.0 * Wl * Wl * math.log2(Wl)
+        nbytes += cnt * (2.0 * Wl * Wl + (128.0 * Wl * Wl if Wl > 64 else 0.0))
+    emit({"row": "multiwindow", "workload": "%d^2 u8 dense speckle, translation (%.1f, %.1f) px + 1 %% / -0.5 %% "
+          "strain, subset %d, step %d, max_disp %d, sub-pixel fit, MAD 2.0" % (
+              w.W, 0.1526 * w.W, -0.0915 * w.W, w.N, w.step, w.max_disp),
+          "levels": r["levels"], "ms": ms, "valid_nodes": nodes, "nodes_per_s": nodes / (ms / 1e3),
+          "window_pairs": nwin, "algorithmic_gflop": flop / 1e9, "algorithmic_gb": nbytes / 1e9,
+          "achieved_tflops": flop / (ms / 1e3) / 1e12, "achieved_GBps": nbytes / (ms / 1e3) / 1e9,
+          "cpu_oracle": {"kind": "oracle", "cores": 1, "sample": "384^2 pair of the same recipe",
+                         "nodes_per_s": float(ro["valid"].sum() / sec), "s": sec}})
+    ms_mw, g = _event_ms(lambda: eng.correlate_mw(d_def, w.seeds, max_disp=w.max_disp), 3)
+    conv = int((g["status"] == 0).sum().item())
+    ms_plain, gp = _event_ms(lambda: eng.correlate(d_def, w.seeds), 1)
+    emit({"row": "correlate_mw", "workload": "as multiwindow; affine, reliability-guided from the estimate",
+          "ms": ms_mw, "converged": conv, "converged_per_s": conv / (ms_mw / 1e3),
+          "plain_seed_search_converged": int((gp["status"] == 0).sum().item())})
+    del d_ref, d_def, d_roi, pair
+
+    # ---- the 2048^2 u8 affine workload: strain, variants, out-of-core
+    w = synth.workload("c1", size=args.size)
+    pair = w.pair()
+    d_ref, d_def = dic.to_device_image(pair.ref), dic.to_device_image(pair.deformed)
+    d_roi = torch.from_numpy(pair.roi).cuda()
+    eng.set_reference(d_ref, d_roi, **w.params())
+    base_ms, base = _event_ms(lambda: eng.correlate(d_def, w.seeds), 3)
+    base_conv = int((base["status"] == 0).sum().item())
+    wl = "%d^2 u8 speckle, affine field, subset %d, step %d" % (w.W, w.N, w.step)
+    emit({"row": "znssd_affine_gn", "workload": wl, "ms": base_ms, "converged": base_conv,
+          "converged_per_s": base_conv / (base_ms / 1e3)})
+    ny, nx = base["status"].shape
+    u, v, stt = base["p"][0].contiguous(), base["p"][1].contiguous(), base["status"].contiguous()
+    us, vs, ss = base["p"][0].cpu().numpy(), base["p"][1].cpu().numpy(), base["status"].cpu().numpy()
+    for win, basis, meas in ((5, "bilinear", "green_lagrange"), (9, "biquadratic", "hencky")):
+        ms, _ = _event_ms(lambda: eng.strain(u, v, stt, step=w.step, window=win, basis=basis, measure=meas), 10)
+        crop = (slice(ny // 2 - 48, ny // 2 + 48), slice(nx // 2 - 48, nx // 2 + 48))
+        sec, _ = _host_s(lambda: OST.strain(us[crop], vs[crop], w.step, win, basis, meas, valid=ss[crop] == 0))
+        nb = nx * ny * (4 + 4 + 1 + 7 * 4)
+        emit({"row": "strain", "workload": "%s result grid %dx%d, window %d, %s, %s" % (wl, nx, ny, win, basis, meas),
+              "ms": ms, "nodes_per_s": nx * ny / (ms / 1e3), "algorithmic_bytes": nb,
+              "achieved_GBps": nb / (ms / 1e3) / 1e9,
+              "cpu_oracle": {"kind": "oracle", "cores": 1, "sample": "96x96-node crop of the same grid",
+                             "nodes_per_s": 96 * 96 / sec, "s": sec}})
+    crop_w = synth.workload("c1", size=512)
+    cpair = crop_w.pair()
+    for name, over in (("rigid_znssd", dict(shape=2)), ("nssd_affine", dict(cost="nssd")),
+                       ("ssd_affine", dict(cost="ssd")), ("znssd_affine_lm", dict(lm_lambda=1e-3)),
+                       ("znssd_quadratic_gn", dict(shape=12))):
+        prm = dict(w.params())
+        prm.update(over)
+        eng.set_reference(d_ref, d_roi, **prm)
+        ms, g = _event_ms(lambda: eng.correlate(d_def, w.seeds), 3)
+        conv = int((g["status"] == 0).sum().item())
+        po = {k: v for k, v in crop_w.params().items() if k not in ("coef_fp16", "reduce_fp64", "threads_per_subset",
+                                                                      "nan_unconverged", "tile_side")}
+        po.update(over)
+        sec, ro = _host_s(lambda: oracle.correlate(cpair.ref, cpair.deformed, cpair.roi, seeds=crop_w.seeds,
+                                                   threads=1, **po))
+        emit({"row": name, "workload": wl, "ms": ms, "converged": conv, "converged_per_s": conv / (ms / 1e3),
+              "vs_znssd_affine_gn": base_ms / ms,
+              "cpu_oracle": {"kind": "oracle", "cores": 1, "sample": "512^2 pair of the same recipe",
+                             "converged_per_s": float((ro["status"] == 0).sum() / sec), "s": sec}})
+    # out-of-core: host images, one band of 32 node rows (+16 halo rows) on the device at a time
+    prm = dict(w.params())
+    ref_h, def_h, roi_h = pair.ref, pair.deformed, pair.roi
+    sec, g = _host_s(lambda: eng.correlate_chunked(ref_h, def_h, roi_h, seeds=w.seeds, band_rows=32, halo=16, **prm))
+    sec2, g = _host_s(lambda: eng.correlate_chunked(ref_h, def_h, roi_h, seeds=w.seeds, band_rows=32, halo=16,
+                                                    **prm))
+    conv = int((g["status"] == 0).sum())
+    po = {k: v for k, v in crop_w.params().items() if k not in ("coef_fp16", "reduce_fp64", "threads_per_subset",
+                                                                  "nan_unconverged", "tile_side")}
+    osec, ro = _host_s(lambda: OCH.correlate_chunked(cpair.ref, cpair.deformed, cpair.roi, seeds=crop_w.seeds,
+                                                     band_rows=8, halo=16, **po))
+    emit({"row": "chunked", "workload": wl + "; host images, bands of 32 node rows, halo 16", "s": min(sec, sec2),
+          "converged": conv, "converged_per_s": conv / min(sec, sec2),
+          "device_resident_ms": base_ms, "band_rows_on_device": 32 * w.step + w.N + 32,
+          "cpu_oracle": {"kind": "oracle", "cores": 1, "sample": "512^2 pair, bands of 8 node rows",
+                         "converged_per_s": float((ro["status"] == 0).sum() / osec), "s": osec}})
+    del d_ref, d_def, d_roi
+
+    # ---- sequence with reference updating: 1024^2, 8 frames of a growing stretch
+    W, F = args.size // 2, 8
+    X, Y, Sg, A = synth.draw_blobs(W, W, int(0.03 * W * W), (1.5, 3.0), (60, 200), 77)
+    ref = synth._finish(synth._render_blobs(W, W, X, Y, Sg, A), 2.0, 78, 8)
+    frames = []
+    for k in range(F):
+        fld = synth.field_affine(0.0, 0.0, dudx=0.03 * k, dvdy=0.03 * k, xc=W / 2, yc=W / 2)
+        uu, vv = fld(X, Y)
+        frames.append(synth._finish(synth._render_blobs(W, W, X + uu, Y + vv, Sg, A), 2.0, 79 + k, 8))
+    roi = np.zeros((W, W), np.uint8)
+    m = W // 5
+    roi[m:W - m, m:W - m] = 1
+    d_roi = torch.from_numpy(roi).cuda()
+    prm = dict(subset_size=21, step=4, seed_radius=3)
+    eng.set_reference(dic.to_device_image(ref), d_roi, **prm)
+    d_frames = [dic.to_device_image(f) for f in frames]
+    seeds = [(W / 2, W / 2, 0, 0)]
+    ms, (outs, refs) = _event_ms(lambda: eng.correlate_sequence(d_frames, seeds, d_roi, min_converged=0.9,
+                                                                min_zncc=0.999), 1)
+    eng.set_reference(dic.to_device_image(ref), d_roi, **prm)
+    ms, (outs, refs) = _event_ms(lambda: eng.correlate_sequence(d_frames, seeds, d_roi, min_converged=0.9,
+                                                                min_zncc=0.999), 1)
+    conv = [int((o["status"] == 0).sum().item()) for o in outs]
+    Ws = 192
+    Xs, Ys, Ss, As = synth.draw_blobs(Ws, Ws, int(0.03 * Ws * Ws), (1.5, 3.0), (60, 200), 77)
+    refs_ = synth._finish(synth._render_blobs(Ws, Ws, Xs, Ys, Ss, As), 2.0, 78, 8)
+    fr_s = []
+    for k in range(4):
+        fld = synth.field_affine(0.0, 0.0, dudx=0.04 * k, dvdy=0.04 * k, xc=Ws / 2, yc=Ws / 2)
+        uu, vv = fld(Xs, Ys)
+        fr_s.append(synth._finish(synth._render_blobs(Ws, Ws, Xs + uu, Ys + vv, Ss, As), 2.0, 79 + k, 8))
+    roi_s = np.zeros((Ws, Ws), np.uint8)
+    roi_s[40:Ws - 40, 40:Ws - 40] = 1
+    osec, (oo, orf) = _host_s(lambda: OSQ.correlate_sequence(refs_, fr_s, roi_s, seeds=[(96, 96, 0, 0)],
+                                                            min_converged=0.9, min_zncc=0.999, **prm))
+    emit({"row": "sequence", "workload": "%d^2 u8 speckle, %d frames, stretch +3 %% per frame in x and y, "
+          "subset 21, step 4, affine, update below 90 %% converged or mean ZNCC 0.999" % (W, F),
+          "ms": ms, "frames_per_s": F / (ms / 1e3), "references": refs, "converged_per_frame": conv,
+          "converged_per_s": sum(conv) / (ms / 1e3),
+          "cpu_oracle": {"kind": "oracle", "cores": 1, "sample": "192^2, 4 frames of +4 % stretch",
+                         "converged_per_s": float(sum((o["status"] == 0).sum() for o in oo) / osec), "s": osec}})
+    eng.close()
+    print(json.dumps({"workload": "entry points beyond the single-pair path", "rows": rows,
+                      "host": host_info(), "s_total": time.perf_counter() - t0}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -654,7 +875,7 @@ def main():
     ap.add_argument("--single-crop", type=int, default=512, help="oracle window on one core (0 = skip)")
     ap.add_argument("--no-fp32-variant", action="store_true",
                     help="skip timing the FP32-reduction variant beside the FP64-reduction default")
-    ap.add_argument("--workload", default="2048", choices=["2048", "gigapixel", "serve", "precision"],
+    ap.add_argument("--workload", default="2048", choices=["2048", "gigapixel", "serve", "precision", "extensions", "roofs"],
                     help="2048: the 2048^2 batched/plain benchmark; gigapixel: the 32768^2 pair, repeated; "
                          "serve: the serving mix")
     ap.add_argument("--precision-size", type=int, default=2048, help="precision: image side")
@@ -670,13 +891,19 @@ def main():
     ap.add_argument("--parity-samples", type=int, default=8, help="serve: requests checked against the oracle")
     ap.add_argument("--summarize-trace", metavar="DIR", help="write the kernel-trace summary of a rocprofv3 run")
     ap.add_argument("--summary-out", default=os.path.join(ROOT, "profiles", "k_wave_2048_kernel_trace.md"))
+    ap.add_argument("--summarize-ext-trace", metavar="DIR",
+                    help="write the kernel-trace summary of a profiled --workload extensions run")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write the HBM counter summary and per-launch traffic from four rocprofv3 --pmc runs")
+    ap.add_argument("--no-probes", action="store_true", help="skip the achievable-rate probes in the roofline")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, args.summary_out)
+        return
+    if args.summarize_ext_trace:
+        summarize_ext_trace(args.summarize_ext_trace, args.summary_out)
         return
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc, os.path.join(ROOT, "profiles", "k_wave_2048_hbm_counters.md"),
@@ -696,6 +923,15 @@ def main():
         return
     if args.workload == "gigapixel":
         gigapixel(args)
+        return
+    if args.workload == "extensions":
+        extensions(args)
+        return
+    if args.workload == "roofs":
+        from paper_2601_12941_amd import roofs
+        print(json.dumps({"workload": "achievable-rate probes (include/dic_roofs.h)", **roofs.measure(),
+                          "published": {"hbm_GBps": PEAK_HBM_GBPS, "fp32_TFLOPs": PEAK_FP32_TFLOPS,
+                                        "fp64_TFLOPs": 78.6}, "host": host_info()}))
         return
 
     import torch
@@ -833,6 +1069,15 @@ def main():
                 "flop_per_px_iter": FLOP_PER_PX_IT[w.shape], "avg_launch_us": avg_launch_ms * 1e3,
                 "launches_per_step": launches / args.steps,
                 "subsets_per_launch": conv / max(1, launches)}
+    # achievable denominators measured on this GPU beside the published peaks: FP32 FMA
+    # issue as the library is built (no packed FP32) and HBM streaming reads
+    if not args.no_probes:
+        from paper_2601_12941_amd import roofs
+        fma32 = roofs.fma(False)
+        hbm = roofs.hbm_read()
+        roofline["achievable"] = {"fma_f32_TFLOPs": fma32, "hbm_read_GBps": hbm,
+                                  "probe": "dic_roof_fma / dic_roof_hbm_read (include/dic_roofs.h)"}
+        roofline["frac_of_achievable"] = achieved / fma32
     if traffic:
         # the same launch against the HBM roof: counted bytes over the live launch time,
         # and the counted bytes over the compulsory ones (each frame's deformed image and
@@ -841,6 +1086,8 @@ def main():
         roofline["traffic_gbps"] = gbps
         roofline["traffic_frac_of_hbm"] = gbps / PEAK_HBM_GBPS
         roofline["traffic_bytes_per_subset"] = traffic / max(1.0, conv / max(1, launches))
+        if "achievable" in roofline:
+            roofline["traffic_frac_of_achievable_hbm"] = gbps / roofline["achievable"]["hbm_read_GBps"]
 
     cpu = None
     acc = None

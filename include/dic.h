@@ -169,6 +169,12 @@ dic_status dic_set_reference(dic_ctx *c, const dic_image *ref, const uint8_t *ro
  * the step.  Any pointer may be NULL. */
 dic_status dic_grid_shape(const dic_ctx *c, int32_t *nx, int32_t *ny, int32_t *x0, int32_t *y0, int32_t *step);
 
+/* Node grid of a width x height image for a subset size and step, without a
+ * context (nodes at h + i*step, i < floor((width - N) / step) + 1).  HOST
+ * outputs; either may be NULL.  DIC_E_INVAL when the subset does not fit or
+ * subset_size or step is below 1. */
+dic_status dic_node_grid(int32_t width, int32_t height, int32_t subset_size, int32_t step, int32_t *nx, int32_t *ny);
+
 /*
  * Correlate one deformed image (same size as the reference) from `nseeds`
  * host seeds; results go to `out` (device arrays, [ny][nx]).

@@ -1,4 +1,5 @@
-"""Build the HIP library (libdicmi.so) for gfx950, in-tree.
+"""Build the HIP library (libdicmi.so) and the device-rate probes
+(libdicroofs.so) for gfx950, in-tree.
 
 hipcc cross-compiles without a GPU.  Packed-FP32 instructions are disabled
 for all device code; FP contraction is controlled inside the sources.
@@ -14,7 +15,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdicmi.so")
-SOURCES = ["dic_kernels.hip", "dic_engine.hip", "dic_server.hip", "dic_strain.hip", "dic_variants.hip", "dic_fft.hip", "dic_sequence.hip", "dic_chunked.hip", "dic_noalloc.hip"]
+ROOFS_LIB = os.path.join(HERE, "libdicroofs.so")
+SOURCES = ["dic_kernels.hip", "dic_engine.hip", "dic_server.hip", "dic_strain.hip", "dic_variants.hip",
+           "dic_fft.hip", "dic_sequence.hip", "dic_chunked.hip", "dic_noalloc.hip"]
+ROOFS_SOURCES = ["dic_roofs.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("DIC_OFFLOAD_ARCH", "gfx950")
 
@@ -58,19 +62,24 @@ def _compile(src: str, build_dir: str) -> str:
     return obj
 
 
-def build(verbose: bool = True) -> str:
-    build_dir = os.path.join(HERE, "_build")
-    os.makedirs(build_dir, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, build_dir), SOURCES))
-    tmp = LIB + ".tmp%d" % os.getpid()
+def _link(objs, lib):
+    tmp = lib + ".tmp%d" % os.getpid()
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (r.stdout, r.stderr))
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = True) -> str:
+    build_dir = os.path.join(HERE, "_build")
+    os.makedirs(build_dir, exist_ok=True)
+    with ThreadPoolExecutor(max_workers=len(SOURCES) + len(ROOFS_SOURCES)) as ex:
+        objs = list(ex.map(lambda s: _compile(s, build_dir), SOURCES + ROOFS_SOURCES))
+    _link(objs[:len(SOURCES)], LIB)
+    _link(objs[len(SOURCES):], ROOFS_LIB)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", ROOFS_LIB)
     return LIB
 
 

@@ -47,7 +47,7 @@ dic_status dic_correlate_chunked(dic_ctx *c, const dic_image *ref_host, const di
     const int W = ref_host->width, H = ref_host->height, N = prm->subset_size, s = prm->step;
     if (N < 5 || (N & 1) == 0 || s < 1 || W < N || H < N) FAIL(DIC_E_INVAL, "subset %d, step %d", N, s);
     const int np = prm->shape, h = (N - 1) / 2;
-    const int nx = (W - N) / s + 1, ny = (H - N) / s + 1;
+    const int nx = grid_count(W, N, s), ny = grid_count(H, N, s);
     const int64_t nn = static_cast<int64_t>(nx) * ny;
     const size_t px = pixel_size(ref_host->pixel), rowb = static_cast<size_t>(W) * px;
     if (ref_host->pitch_bytes < static_cast<int64_t>(rowb) || def_host->pitch_bytes < static_cast<int64_t>(rowb))
@@ -80,7 +80,7 @@ dic_status dic_correlate_chunked(dic_ctx *c, const dic_image *ref_host, const di
     int16_t *d_it = nullptr;
     int8_t *d_st = nullptr;
     int32_t *d_wv = nullptr;
-    const int64_t max_nodes = static_cast<int64_t>(nx) * ((max_rows - N) / s + 1);
+    const int64_t max_nodes = static_cast<int64_t>(nx) * grid_count(max_rows, N, s);
     auto release = [&]() {
         dfree(d_ref);
         dfree(d_def);

@@ -24,6 +24,9 @@ struct FrameBuf {
     unsigned long long *stat = nullptr;
 };
 
+// Nodes along one image extent: centres h + i*step while the subset fits.
+inline int grid_count(int extent, int subset_size, int step) { return (extent - subset_size) / step + 1; }
+
 inline size_t pixel_size(int pixel) { return pixel == DIC_PIX_U8 ? 1 : (pixel == DIC_PIX_U16 ? 2 : 4); }
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }

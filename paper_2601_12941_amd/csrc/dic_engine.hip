@@ -91,6 +91,14 @@ dic_status dic_grid_shape(const dic_ctx *c, int32_t *nx, int32_t *ny, int32_t *x
     return DIC_OK;
 }
 
+dic_status dic_node_grid(int32_t width, int32_t height, int32_t subset_size, int32_t step, int32_t *nx, int32_t *ny)
+{
+    if (subset_size < 1 || step < 1 || width < subset_size || height < subset_size) return DIC_E_INVAL;
+    if (nx) *nx = grid_count(width, subset_size, step);
+    if (ny) *ny = grid_count(height, subset_size, step);
+    return DIC_OK;
+}
+
 dic_status dic_get_stats(const dic_ctx *c, dic_stats *out)
 {
     if (!c || !out) return DIC_E_INVAL;
@@ -144,8 +152,8 @@ dic_status dic_set_reference(dic_ctx *c, const dic_image *ref, const uint8_t *ro
     c->variant = variant;
     c->W = ref->width;
     c->H = ref->height;
-    c->nx = (c->W - p.subset_size) / p.step + 1;
-    c->ny = (c->H - p.subset_size) / p.step + 1;
+    c->nx = grid_count(c->W, p.subset_size, p.step);
+    c->ny = grid_count(c->H, p.subset_size, p.step);
     c->nodes = static_cast<int64_t>(c->nx) * c->ny;
     c->ref_pixel = ref->pixel;
     c->cpitch = round_up(c->W + 2 * kPad, 64);

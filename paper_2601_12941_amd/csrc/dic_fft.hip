@@ -3,23 +3,26 @@
 // correlation of square windows, from windows larger than the expected
 // displacement down to one window per node of the subset grid.
 //
-// Per level, every window pair goes through one batched pipeline on the GPU:
+// Per level, every window pair goes through one pipeline on the GPU:
 //   load      z = w f + i w g (the two Hann-tapered real windows packed into one
 //             complex array, so one complex transform yields both spectra);
-//   fft2      rows in LDS (radix-2 Stockham, FP32), transpose, rows again;
+//   fft2      radix-2 Stockham transforms in LDS (FP32), rows then columns;
 //   cross     F conj(G) / (|F| |G|) with F, G split from Z by its Hermitian
 //             symmetry;
 //   ifft2     the same passes inverse;
-//   peak      argmax of the real map per window (one workgroup), the integer
-//             displacement shift - q, and on the node level the 3-point Gaussian
-//             sub-pixel fit;
+//   peak      argmax of the real map per window, the integer displacement
+//             shift - q, and on the node level the 3-point Gaussian sub-pixel fit;
 //   mad       the 3x3 normalised-median test on the level's integer field;
 //   guess     the next level's integer guesses by exact bilinear interpolation.
+// Windows of up to 64 samples (the node level and the finest regular levels)
+// run load to peak in one kernel with the windows resident in LDS, so their
+// only memory traffic is the pixels and the estimates.  Larger windows go
+// through batch buffers in HBM: load, rows, transpose, rows, cross, the same
+// inverse, and a two-step peak search (parts of each map, then per window).
 // Readings (window schedule, grids, taper, tie rules, MAD constants) follow the
 // FP64 reference implementation of the same procedure; the integer steps are
 // exact, so they agree bit for bit, and only the FFT's FP32 rounding can move a
-// peak when two map values nearly tie.  HBM-bound: each window pair is read once
-// and its W^2 complex values make three round trips through the batch buffers.
+// peak when two map values nearly tie.
 #include "dic_context.h"
 
 #include <climits>
@@ -33,6 +36,8 @@ constexpr int kFftThreads = 256;
 constexpr int kMaxLevels = 32;
 constexpr int64_t kBatchElems = int64_t(1) << 24;   // complex values per batch buffer (128 MiB)
 constexpr int kMaxWindow = 4096;   // largest window: two rows of it fill 64 KiB of LDS
+constexpr int kMaxFusedWindow = 64; // windows up to this side run the whole pipeline in LDS
+constexpr int kMaxTableWindow = 2048; // row transforms up to this length read twiddles from an LDS table
 
 // Geometry of one level: windows of side W centred at (ox + i S, oy + j S).
 struct Level {
@@ -86,6 +91,18 @@ __global__ void k_mw_load(Level L, int w0, int count, const void *ref, int64_t r
     z[e] = v;
 }
 
+// Twiddle table of a length-W transform: tw[m] = (sin, cos) of sgn pi 2m / W for
+// m < W / 2, the values sincospif gives for sgn pi k / Ns at m = k W / (2 Ns) (the
+// arguments are the same dyadic fractions, so the table changes no bit).
+__device__ __forceinline__ void twiddles(float2 *tw, int W, float sgn)
+{
+    for (int m = threadIdx.x; m < W / 2; m += blockDim.x) {
+        float sn, cs;
+        sincospif(sgn * static_cast<float>(2 * m) / static_cast<float>(W), &sn, &cs);
+        tw[m] = make_float2(sn, cs);
+    }
+}
+
 // One radix-2 Stockham transform of length W per row, in LDS (FP32): a
 // workgroup takes max(1, 1024 / W) consecutive rows.  INV: exp(+i ...), unscaled.
 template <bool INV>
@@ -94,20 +111,28 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows(float2 *data, int W, i
     extern __shared__ float2 lds[];
     const int R = W >= 1024 ? 1 : 1024 / W;
     const int tot = R * W, half = W / 2;
-    float2 *x = lds, *y = lds + tot;
+    float2 *x = lds, *y = lds + tot, *tw = lds + 2 * tot;
     const int64_t row0 = static_cast<int64_t>(blockIdx.x) * R;
     const int rows = static_cast<int>(min<int64_t>(R, nrows - row0));
     float2 *g = data + row0 * W;
-    for (int e = threadIdx.x; e < rows * W; e += kFftThreads) x[e] = g[e];
-    __syncthreads();
+    const bool table = W <= kMaxTableWindow;   // the largest windows evaluate their twiddles
     const float sgn = INV ? 1.0f : -1.0f;
+    for (int e = threadIdx.x; e < rows * W; e += kFftThreads) x[e] = g[e];
+    if (table) twiddles(tw, W, sgn);
+    __syncthreads();
     for (int Ns = 1; Ns < W; Ns <<= 1) {
+        const int tstep = half / Ns;
         for (int b = threadIdx.x; b < rows * half; b += kFftThreads) {
             const int r = b / half, j = b - (b / half) * half;
             const int base = r * W, k = j & (Ns - 1);
             const float2 a0 = x[base + j], a1 = x[base + j + half];
             float s, c;
-            sincospif(sgn * static_cast<float>(k) / static_cast<float>(Ns), &s, &c);
+            if (table) {
+                s = tw[k * tstep].x;
+                c = tw[k * tstep].y;
+            } else {
+                sincospif(sgn * static_cast<float>(k) / static_cast<float>(Ns), &s, &c);
+            }
             const float2 t = make_float2(a1.x * c - a1.y * s, a1.x * s + a1.y * c);
             const int d = base + ((j - k) << 1) + k;
             y[d] = make_float2(a0.x + t.x, a0.y + t.y);
@@ -180,66 +205,266 @@ __device__ __forceinline__ float gauss3(float a, float b, float c)
     return fabsf(e) <= 0.5f ? e : 0.0f;
 }
 
-// Peak of every window's real map (one workgroup per window): integer estimate
-// shift - q into (iu, iv); with `sub`, the Gaussian fit into (fu, fv).
-__global__ __launch_bounds__(kFftThreads) void k_mw_peak(const float2 *r, int W, int w0, const int32_t *gu,
-                                                          const int32_t *gv, const uint8_t *skip, int32_t *iu,
-                                                          int32_t *iv, float *fu, float *fv, int sub)
+// Peak search of the large windows in two steps.  First every map is cut into
+// B = W^2 / kPeakChunk parts and one workgroup finds the best element of each
+// part (value, map index) under the total order below; then one workgroup per
+// window picks the best of its B parts and writes the estimate.
+constexpr int kPeakChunk = 16384;
+
+__device__ __forceinline__ int signed_q(int i, int W) { return i < W / 2 ? i : i - W; }
+
+// the order on map indices: larger value, then smaller |q|^2, qy, qx; an index
+// holding NaN never wins (a map with no number keeps the window's guess)
+__device__ __forceinline__ bool index_better(float v, int e, float bv, int be, int W)
+{
+    if (e < 0 || !(v == v)) return false;
+    if (be < 0) return true;
+    return peak_better(v, signed_q(e % W, W), signed_q(e / W, W), bv, signed_q(be % W, W), signed_q(be / W, W));
+}
+
+__device__ __forceinline__ void block_best(float &bv, int &be, int W)
 {
     __shared__ float sv[kFftThreads];
-    __shared__ int sx[kFftThreads], sy[kFftThreads];
-    const int w = w0 + blockIdx.x;
+    __shared__ int se[kFftThreads];
     const int t = threadIdx.x;
-    if (skip[w]) {
-        if (t == 0) {
-            iu[w] = gu[w];
-            iv[w] = gv[w];
-            if (fu) {
-                fu[w] = static_cast<float>(gu[w]);
-                fv[w] = static_cast<float>(gv[w]);
-            }
-        }
-        return;
-    }
-    const float2 *m = r + static_cast<int64_t>(blockIdx.x) * W * W;
-    float bv = -INFINITY;
-    int bx = INT_MAX / 4, by = INT_MAX / 4;
-    for (int e = t; e < W * W; e += kFftThreads) {
-        const int y = e / W, x = e - (e / W) * W;
-        const int qx = x < W / 2 ? x : x - W, qy = y < W / 2 ? y : y - W;
-        const float v = m[e].x;
-        if (peak_better(v, qx, qy, bv, bx, by)) {
-            bv = v;
-            bx = qx;
-            by = qy;
-        }
-    }
     sv[t] = bv;
-    sx[t] = bx;
-    sy[t] = by;
+    se[t] = be;
     __syncthreads();
-    for (int s = kFftThreads / 2; s > 0; s >>= 1) {
-        if (t < s && peak_better(sv[t + s], sx[t + s], sy[t + s], sv[t], sx[t], sy[t])) {
-            sv[t] = sv[t + s];
-            sx[t] = sx[t + s];
-            sy[t] = sy[t + s];
+    for (int st = kFftThreads / 2; st > 0; st >>= 1) {
+        if (t < st && index_better(sv[t + st], se[t + st], sv[t], se[t], W)) {
+            sv[t] = sv[t + st];
+            se[t] = se[t + st];
         }
         __syncthreads();
     }
-    if (t == 0) {
-        const int qx = sx[0], qy = sy[0];
+    bv = sv[0];
+    be = se[0];
+}
+
+// part results as (value, index bits) pairs in `part` (cnt * B entries)
+__global__ __launch_bounds__(kFftThreads) void k_mw_peak_part(const float2 *r, int W, int B, float2 *part)
+{
+    const int wl = blockIdx.x / B, pi = blockIdx.x - (blockIdx.x / B) * B;
+    const int64_t WW = static_cast<int64_t>(W) * W;
+    const int chunk = static_cast<int>(WW / B);
+    const float2 *m = r + static_cast<int64_t>(wl) * WW;
+    float bv = -INFINITY;
+    int be = -1;
+    for (int e = pi * chunk + threadIdx.x; e < (pi + 1) * chunk; e += kFftThreads)
+        if (index_better(m[e].x, e, bv, be, W)) {
+            bv = m[e].x;
+            be = e;
+        }
+    block_best(bv, be, W);
+    if (threadIdx.x == 0) part[blockIdx.x] = make_float2(bv, __int_as_float(be));
+}
+
+// integer estimate shift - q into (iu, iv); with `sub`, the Gaussian fit into (fu, fv)
+__global__ __launch_bounds__(kFftThreads) void k_mw_peak(const float2 *r, const float2 *part, int B, int W, int w0,
+                                                          const int32_t *gu, const int32_t *gv, const uint8_t *skip,
+                                                          int32_t *iu, int32_t *iv, float *fu, float *fv, int sub)
+{
+    const int w = w0 + blockIdx.x;
+    float bv = -INFINITY;
+    int be = -1;
+    if (!skip[w]) {
+        for (int i = threadIdx.x; i < B; i += kFftThreads) {
+            const float2 pv = part[static_cast<int64_t>(blockIdx.x) * B + i];
+            if (index_better(pv.x, __float_as_int(pv.y), bv, be, W)) {
+                bv = pv.x;
+                be = __float_as_int(pv.y);
+            }
+        }
+        block_best(bv, be, W);
+    }
+    if (threadIdx.x == 0 && be < 0) {       // skipped, or no number in the map: keep the guess
+        iu[w] = gu[w];
+        iv[w] = gv[w];
+        if (fu) {
+            fu[w] = static_cast<float>(gu[w]);
+            fv[w] = static_cast<float>(gv[w]);
+        }
+    } else if (threadIdx.x == 0) {
+        const float2 *m = r + static_cast<int64_t>(blockIdx.x) * W * W;
+        const int px = be % W, py = be / W;
+        const int qx = signed_q(px, W), qy = signed_q(py, W);
         iu[w] = gu[w] - qx;
         iv[w] = gv[w] - qy;
         if (fu) {
             float ex = 0.0f, ey = 0.0f;
             if (sub) {
-                const int px = (qx + W) & (W - 1), py = (qy + W) & (W - 1);
                 const float b = m[py * W + px].x;
                 ex = gauss3(m[py * W + ((px + W - 1) & (W - 1))].x, b, m[py * W + ((px + 1) & (W - 1))].x);
                 ey = gauss3(m[((py + W - 1) & (W - 1)) * W + px].x, b, m[((py + 1) & (W - 1)) * W + px].x);
             }
             fu[w] = static_cast<float>(gu[w] - qx) - ex;
             fv[w] = static_cast<float>(gv[w] - qy) - ey;
+        }
+    }
+}
+
+// One radix-2 Stockham stage over `lines` transforms of length W held in LDS:
+// element e of line l sits at base(l) + e * es; lines are rows (es = 1) or
+// columns (es = the row pitch) of K windows of W rows each.
+template <int W>
+__device__ __forceinline__ void lds_stage(const float2 *x, float2 *y, int lines, int pitch, bool cols, int Ns,
+                                          const float2 *tw)
+{
+    constexpr int half = W / 2;
+    const int es = cols ? pitch : 1, tstep = half / Ns;
+    for (int b = threadIdx.x; b < lines * half; b += kFftThreads) {
+        const int l = b / half, j = b - (b / half) * half;
+        const int win = l / W, r = l - (l / W) * W;
+        const int base = win * W * pitch + (cols ? r : r * pitch);
+        const int k = j & (Ns - 1);
+        const float2 a0 = x[base + j * es], a1 = x[base + (j + half) * es];
+        const float sn = tw[k * tstep].x, cs = tw[k * tstep].y;
+        const float2 t = make_float2(a1.x * cs - a1.y * sn, a1.x * sn + a1.y * cs);
+        const int d = ((j - k) << 1) + k;
+        y[base + d * es] = make_float2(a0.x + t.x, a0.y + t.y);
+        y[base + (d + Ns) * es] = make_float2(a0.x - t.x, a0.y - t.y);
+    }
+}
+
+// 2-D transform of K windows in LDS (rows, then columns); returns the buffer
+// holding the result (x or y).
+template <int W>
+__device__ __forceinline__ float2 *lds_fft2(float2 *x, float2 *y, int K, int pitch, const float2 *tw)
+{
+    for (int pass = 0; pass < 2; ++pass)
+        for (int Ns = 1; Ns < W; Ns <<= 1) {
+            lds_stage<W>(x, y, K * W, pitch, pass == 1, Ns, tw);
+            __syncthreads();
+            float2 *t = x;
+            x = y;
+            y = t;
+        }
+    return x;
+}
+
+// The whole per-window pipeline of the small levels (W <= 64) in LDS, K =
+// max(1, 1024 / W^2) windows per workgroup: load and taper, forward transform,
+// normalised cross-power, inverse transform, peak and sub-pixel fit.  The
+// arithmetic is that of the batched pipeline (same butterflies, twiddles,
+// cross-power, tie order and fit); only the order of the two 1-D passes of the
+// 2-D transforms differs (rows then columns in place, instead of rows,
+// transpose, rows).  HBM traffic: the two windows' pixels and the outputs.
+template <int W>
+__global__ __launch_bounds__(kFftThreads) void k_mw_fused(Level L, int count, const void *ref, int64_t rpitch,
+                                                           int rpix, const void *def, int64_t dpitch, int dpix,
+                                                           int imgW, int imgH, const int32_t *gu, const int32_t *gv,
+                                                           const int8_t *active, int32_t *iu, int32_t *iv, float *fu,
+                                                           float *fv, int sub)
+{
+    constexpr int K = W * W >= 1024 ? 1 : 1024 / (W * W);
+    constexpr int P = W + 1;                     // row pitch: column passes avoid bank conflicts
+    constexpr int kSz = K * W * P;
+    __shared__ float2 buf[2 * kSz];
+    __shared__ float2 twf[W / 2], twi[W / 2];
+    __shared__ float sv[kFftThreads];
+    __shared__ int sq[kFftThreads];
+    __shared__ uint8_t skipw[K];
+    const int w0 = blockIdx.x * K;
+    const int nk = min(K, count - w0);
+    float2 *x = buf, *y = buf + kSz;
+    twiddles(twf, W, -1.0f);
+    twiddles(twi, W, 1.0f);
+    // load: z = w f + i w g
+    for (int e = threadIdx.x; e < K * W * W; e += kFftThreads) {
+        const int k = e / (W * W), q = e - k * (W * W);
+        const int yy = q / W, xx = q - (q / W) * W;
+        float2 v = make_float2(0.0f, 0.0f);
+        bool out = true;
+        if (k < nk) {
+            const int w = w0 + k;
+            int rx, ry;
+            window_origin(L, w, imgW, imgH, rx, ry);
+            const int gx = rx + gu[w], gy = ry + gv[w];
+            out = gx < 0 || gy < 0 || gx > imgW - W || gy > imgH - W || (active && active[w] < 0);
+            if (!out) {
+                const float sx = sinpif(static_cast<float>(xx) / W), sy = sinpif(static_cast<float>(yy) / W);
+                const float t = (sx * sx) * (sy * sy);
+                v.x = t * pixel_at(ref, rpitch, rpix, rx + xx, ry + yy);
+                v.y = t * pixel_at(def, dpitch, dpix, gx + xx, gy + yy);
+            }
+        }
+        if (q == 0) skipw[k] = out ? 1 : 0;
+        x[k * W * P + yy * P + xx] = v;
+    }
+    __syncthreads();
+    float2 *z = lds_fft2<W>(x, y, K, P, twf);
+    float2 *r = z == buf ? buf + kSz : buf;
+    // normalised cross-power of Eq. (1) from the packed spectrum
+    for (int e = threadIdx.x; e < K * W * W; e += kFftThreads) {
+        const int k = e / (W * W), q = e - k * (W * W);
+        const int a = q / W, b = q - (q / W) * W;
+        const int na = (W - a) & (W - 1), nb = (W - b) & (W - 1);
+        const float2 zz = z[k * W * P + a * P + b], zm = z[k * W * P + na * P + nb];
+        const float2 F = make_float2(0.5f * (zz.x + zm.x), 0.5f * (zz.y - zm.y));
+        const float2 G = make_float2(0.5f * (zz.y + zm.y), -0.5f * (zz.x - zm.x));
+        const float cr = F.x * G.x + F.y * G.y, ci = F.y * G.x - F.x * G.y;
+        const float mag = hypotf(F.x, F.y) * hypotf(G.x, G.y);
+        r[k * W * P + a * P + b] = mag > 0.0f ? make_float2(cr / mag, ci / mag) : make_float2(0.0f, 0.0f);
+    }
+    __syncthreads();
+    const float2 *m = lds_fft2<W>(r, z, K, P, twi);
+    // peak per window: the K windows' elements are spread over the threads in
+    // groups of kFftThreads / K consecutive threads
+    constexpr int G = kFftThreads / K;
+    const int k = threadIdx.x / G, tl = threadIdx.x - k * G;
+    float bv = -INFINITY;
+    int bx = INT_MAX / 4, by = INT_MAX / 4;
+    for (int q = tl; q < W * W; q += G) {
+        const int yy = q / W, xx = q - (q / W) * W;
+        const int qx = xx < W / 2 ? xx : xx - W, qy = yy < W / 2 ? yy : yy - W;
+        const float v = m[k * W * P + yy * P + xx].x;
+        if (peak_better(v, qx, qy, bv, bx, by)) {
+            bv = v;
+            bx = qx;
+            by = qy;
+        }
+    }
+    sv[threadIdx.x] = bv;
+    sq[threadIdx.x] = ((by + W) & (W - 1)) * W + ((bx + W) & (W - 1));
+    __syncthreads();
+    for (int st = G / 2; st > 0; st >>= 1) {
+        if (tl < st) {
+            const int o = threadIdx.x + st;
+            const int oq = sq[o], cq = sq[threadIdx.x];
+            const int ox = oq % W, oy = oq / W, cx = cq % W, cy = cq / W;
+            if (peak_better(sv[o], ox < W / 2 ? ox : ox - W, oy < W / 2 ? oy : oy - W, sv[threadIdx.x],
+                            cx < W / 2 ? cx : cx - W, cy < W / 2 ? cy : cy - W)) {
+                sv[threadIdx.x] = sv[o];
+                sq[threadIdx.x] = oq;
+            }
+        }
+        __syncthreads();
+    }
+    if (tl == 0 && k < nk) {
+        const int w = w0 + k;
+        if (skipw[k] || sv[threadIdx.x] == -INFINITY) {    // skipped, or no number in the map
+            iu[w] = gu[w];
+            iv[w] = gv[w];
+            if (fu) {
+                fu[w] = static_cast<float>(gu[w]);
+                fv[w] = static_cast<float>(gv[w]);
+            }
+        } else {
+            const int px = sq[threadIdx.x] % W, py = sq[threadIdx.x] / W;
+            const int qx = px < W / 2 ? px : px - W, qy = py < W / 2 ? py : py - W;
+            iu[w] = gu[w] - qx;
+            iv[w] = gv[w] - qy;
+            if (fu) {
+                float ex = 0.0f, ey = 0.0f;
+                if (sub) {
+                    const float2 *mk = m + k * W * P;
+                    const float b = mk[py * P + px].x;
+                    ex = gauss3(mk[py * P + ((px + W - 1) & (W - 1))].x, b, mk[py * P + ((px + 1) & (W - 1))].x);
+                    ey = gauss3(mk[((py + W - 1) & (W - 1)) * P + px].x, b, mk[((py + 1) & (W - 1)) * P + px].x);
+                }
+                fu[w] = static_cast<float>(gu[w] - qx) - ex;
+                fv[w] = static_cast<float>(gv[w] - qy) - ey;
+            }
         }
     }
 }
@@ -386,6 +611,24 @@ int mw_levels(int max_disp, int N, int W, int H, int *sizes, int *wf)
 
 namespace {
 
+void launch_fused(const Level &L, int count, const void *ref, int64_t rpitch, int rpix, const void *def,
+                  int64_t dpitch, int dpix, int imgW, int imgH, const int32_t *gu, const int32_t *gv,
+                  const int8_t *active, int32_t *iu, int32_t *iv, float *fu, float *fv, int sub, hipStream_t s)
+{
+    const int K = L.W * L.W >= 1024 ? 1 : 1024 / (L.W * L.W);
+    const unsigned nb = static_cast<unsigned>((count + K - 1) / K);
+#define DIC_MW_FUSED(WIN)                                                                                          \
+    k_mw_fused<WIN><<<nb, kFftThreads, 0, s>>>(L, count, ref, rpitch, rpix, def, dpitch, dpix, imgW, imgH, gu, gv, \
+                                               active, iu, iv, fu, fv, sub)
+    switch (L.W) {
+    case 8: DIC_MW_FUSED(8); break;
+    case 16: DIC_MW_FUSED(16); break;
+    case 32: DIC_MW_FUSED(32); break;
+    default: DIC_MW_FUSED(64); break;
+    }
+#undef DIC_MW_FUSED
+}
+
 // one FFT2 of `count` W x W matrices: rows of a, transpose into b, rows of b; the
 // result is in b, transposed relative to the input (the cross spectrum is
 // element-wise and the inverse pass transposes back)
@@ -393,7 +636,7 @@ template <bool INV> void fft2_batch(float2 *a, float2 *b, int W, int count, hipS
 {
     const int R = W >= 1024 ? 1 : 1024 / W;
     const int64_t rows = static_cast<int64_t>(W) * count;
-    const size_t lds = 2 * sizeof(float2) * static_cast<size_t>(R) * W;
+    const size_t lds = sizeof(float2) * (2 * static_cast<size_t>(R) * W + (W <= kMaxTableWindow ? W / 2 : 0));
     const unsigned nb = static_cast<unsigned>((rows + R - 1) / R);
     k_fft_rows<INV><<<nb, kFftThreads, lds, s>>>(a, W, rows);
     const int T = W < 32 ? W : 32;
@@ -480,7 +723,13 @@ dic_status dic_multiwindow(dic_ctx *c, const dic_image *def, const dic_mw_params
         k_mw_guess<<<blocks_for(M, 256), 256, 0, s>>>(L, P, l > 0 ? 1 : 0, pu, pv, gu, gv);
         const int64_t WW = static_cast<int64_t>(L.W) * L.W;
         const int per = static_cast<int>(std::max<int64_t>(1, kBatchElems / WW));
-        for (int64_t w0 = 0; w0 < M; w0 += per) {
+        if (L.W <= kMaxFusedWindow) {
+            launch_fused(L, static_cast<int>(M), c->ref_raw, static_cast<int64_t>(c->W) * pixel_size(c->ref_pixel),
+                         c->ref_pixel, def->data, def->pitch_bytes, def->pixel, c->W, c->H, gu, gv,
+                         node_level ? c->flag : nullptr, cu, cv, node_level ? fu : nullptr,
+                         node_level ? fv : nullptr, node_level && prm->subpixel ? 1 : 0, s);
+        }
+        for (int64_t w0 = 0; L.W > kMaxFusedWindow && w0 < M; w0 += per) {
             const int cnt = static_cast<int>(std::min<int64_t>(per, M - w0));
             const int64_t tot = WW * cnt;
             k_mw_load<<<blocks_for(tot, 256), 256, 0, s>>>(L, static_cast<int>(w0), cnt, c->ref_raw,
@@ -491,7 +740,10 @@ dic_status dic_multiwindow(dic_ctx *c, const dic_image *def, const dic_mw_params
             fft2_batch<false>(za, zb, L.W, cnt, s);   // spectrum [kx][ky] in zb
             k_mw_cross<<<blocks_for(tot, 256), 256, 0, s>>>(zb, za, L.W, tot);
             fft2_batch<true>(za, zb, L.W, cnt, s);    // map [y][x] in zb
-            k_mw_peak<<<cnt, kFftThreads, 0, s>>>(zb, L.W, static_cast<int>(w0), gu, gv, skip, cu, cv,
+            // za is free again: it holds the part results of the peak search
+            const int B = static_cast<int>(std::max<int64_t>(1, WW / kPeakChunk));
+            k_mw_peak_part<<<static_cast<unsigned>(cnt * B), kFftThreads, 0, s>>>(zb, L.W, B, za);
+            k_mw_peak<<<cnt, kFftThreads, 0, s>>>(zb, za, B, L.W, static_cast<int>(w0), gu, gv, skip, cu, cv,
                                                   node_level ? fu : nullptr, node_level ? fv : nullptr,
                                                   node_level && prm->subpixel ? 1 : 0);
         }

