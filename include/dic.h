@@ -169,6 +169,18 @@ dic_status dic_set_reference(dic_ctx *c, const dic_image *ref, const uint8_t *ro
  * the step.  Any pointer may be NULL. */
 dic_status dic_grid_shape(const dic_ctx *c, int32_t *nx, int32_t *ny, int32_t *x0, int32_t *y0, int32_t *step);
 
+/* Copies of the current reference's precompute, for inspection (Sec. 2.2's
+ * cubic B-spline interpolation of the reference): each non-NULL output is a
+ * caller-allocated DEVICE array [height][width] (pitch = width) of FP32.
+ *   coef_out: the prefilter's coefficients as stored, 1/36 of the classical
+ *             B-spline coefficients (the interpolation weights are 6 times the
+ *             B-spline's on each axis, so the interpolant is unchanged);
+ *   f_out, fx_out, fy_out: the interpolant and its x and y derivatives at every
+ *             integer pixel (the reference values and gradients the iteration
+ *             uses).
+ * DIC_E_STATE before dic_set_reference. */
+dic_status dic_reference_arrays(dic_ctx *c, float *coef_out, float *f_out, float *fx_out, float *fy_out);
+
 /* Node grid of a width x height image for a subset size and step, without a
  * context (nodes at h + i*step, i < floor((width - N) / step) + 1).  HOST
  * outputs; either may be NULL.  DIC_E_INVAL when the subset does not fit or

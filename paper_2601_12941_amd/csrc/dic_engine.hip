@@ -91,6 +91,26 @@ dic_status dic_grid_shape(const dic_ctx *c, int32_t *nx, int32_t *ny, int32_t *x
     return DIC_OK;
 }
 
+dic_status dic_reference_arrays(dic_ctx *c, float *coef_out, float *f_out, float *fx_out, float *fy_out)
+{
+    if (!c) return DIC_E_INVAL;
+    c->err.clear();
+    if (!c->has_ref) FAIL(DIC_E_STATE, "dic_reference_arrays before dic_set_reference");
+    HIPCHK(hipSetDevice(c->device));
+    const size_t row = sizeof(float) * c->W;
+    if (coef_out)
+        HIPCHK(hipMemcpy2DAsync(coef_out, row, c->ref_coef_base + kPad * c->cpitch + kPad, sizeof(float) * c->cpitch,
+                                row, c->H, hipMemcpyDeviceToDevice, c->stream));
+    const float *src[3] = {c->pf, c->pfx, c->pfy};
+    float *dst[3] = {f_out, fx_out, fy_out};
+    for (int a = 0; a < 3; ++a)
+        if (dst[a])
+            HIPCHK(hipMemcpy2DAsync(dst[a], row, src[a], sizeof(float) * c->ppitch, row, c->H,
+                                    hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return DIC_OK;
+}
+
 dic_status dic_node_grid(int32_t width, int32_t height, int32_t subset_size, int32_t step, int32_t *nx, int32_t *ny)
 {
     if (subset_size < 1 || step < 1 || width < subset_size || height < subset_size) return DIC_E_INVAL;

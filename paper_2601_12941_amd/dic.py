@@ -29,7 +29,8 @@ NODE = dict(CONVERGED=0, NOT_REACHED=1, NOT_IN_ROI=2, MAX_ITER=3, LOW_ZNCC=4, OU
             FLAT_DEF=7, SINGULAR=8, NAN=9)
 
 # exported names, in the order include/dic.h declares them
-EXPORTS = ["dic_create", "dic_set_reference", "dic_grid_shape", "dic_node_grid", "dic_correlate",
+EXPORTS = ["dic_create", "dic_set_reference", "dic_grid_shape", "dic_reference_arrays", "dic_node_grid",
+           "dic_correlate",
            "dic_correlate_batch", "dic_correlate_noalloc", "dic_noalloc_scratch_bytes", "dic_get_stats",
            "dic_destroy", "dic_last_error", "dic_multiwindow", "dic_correlate_mw", "dic_correlate_sequence",
            "dic_correlate_chunked", "dic_strain", "dic_vsg", "dic_server_create", "dic_server_add_reference",
@@ -119,6 +120,7 @@ def load_library(path: str = LIB_PATH):
     L.dic_set_reference.argtypes = [C.c_void_p, P(DicImage), C.c_void_p, P(DicParams)]
     L.dic_grid_shape.argtypes = [C.c_void_p] + [P(C.c_int32)] * 5
     L.dic_node_grid.argtypes = [C.c_int32] * 4 + [P(C.c_int32)] * 2
+    L.dic_reference_arrays.argtypes = [C.c_void_p] * 5
     L.dic_correlate.argtypes = [C.c_void_p, P(DicImage), P(DicSeed), C.c_int32, P(DicResult)]
     L.dic_correlate_batch.argtypes = [C.c_void_p, P(DicImage), C.c_int32, P(DicSeed), C.c_int32, P(DicResult)]
     L.dic_correlate_noalloc.argtypes = [C.c_void_p, P(DicImage), P(DicSeed), C.c_int32, P(DicResult)]
@@ -476,6 +478,15 @@ class Engine:
                                                                        float(min_zncc)), list(ress))
         return list(outs), refs
 
+    def reference_arrays(self):
+        """dic_reference_arrays: the current reference's stored coefficients (1/36 of
+        the classical ones), interpolant and gradient, as device tensors [H][W]."""
+        import torch
+        H, W = self.ref.shape
+        out = {k: torch.empty((H, W), dtype=torch.float32, device=self.device) for k in ("coef", "f", "fx", "fy")}
+        dic_reference_arrays(self.ctx, *[out[k].data_ptr() for k in ("coef", "f", "fx", "fy")])
+        return out
+
     def correlate_chunked(self, ref, deformed, roi=None, *, seeds, band_rows, halo, boundary_seeds=8, **params):
         """dic_correlate_chunked on HOST numpy images (uint8, uint16 or float32
         [H][W]) and an optional host uint8 ROI: the whole grid's result as host
@@ -544,6 +555,11 @@ def _roi_ptr(roi, ref) -> int:
     if roi.dtype != torch.uint8 or not roi.is_cuda or not roi.is_contiguous() or tuple(roi.shape) != tuple(ref.shape):
         raise ValueError("roi must be a contiguous uint8 device tensor shaped like the image")
     return roi.data_ptr()
+
+
+def dic_reference_arrays(ctx, coef_ptr: int, f_ptr: int, fx_ptr: int, fy_ptr: int):
+    _check(ctx, load_library().dic_reference_arrays(ctx, *[C.c_void_p(x or 0) for x in (coef_ptr, f_ptr, fx_ptr,
+                                                                                        fy_ptr)]))
 
 
 def dic_node_grid(width: int, height: int, subset_size: int, step: int):
