@@ -307,6 +307,7 @@ __global__ __launch_bounds__(T) void k_ref_nodes(RefView R, double *cache, int8_
 {
     constexpr int NH = NP * (NP + 1) / 2;
     constexpr int NB = NP + NH;
+    constexpr int kNC = 3 + 2 * NP + NH;        // per-node cache slots, contiguous per node
     constexpr int NW = T / 64;
     constexpr int CH = NB < 32 ? NB : 32;      // group-B entries per LDS pass
     constexpr int LS = 33;                      // LDS row stride (doubles) of one entry
@@ -367,11 +368,12 @@ __global__ __launch_bounds__(T) void k_ref_nodes(RefView R, double *cache, int8_
         for (int i = 0; i < 3 + NP; ++i) va[i] = static_cast<double>(s[i]);
         block_allreduce<T, 3 + NP>(va, red, parity);
         if (t == 0) {
-            cache[node] = fm;
-            cache[1 * nn + node] = va[1];
-            cache[2 * nn + node] = va[0];
+            double *cn = cache + node * kNC;
+            cn[0] = fm;
+            cn[1] = va[1];
+            cn[2] = va[0];
 #pragma unroll
-            for (int a = 0; a < NP; ++a) cache[(3 + NP + a) * nn + node] = va[3 + a];
+            for (int a = 0; a < NP; ++a) cn[3 + NP + a] = va[3 + a];
         }
         // group B: lanes 2k and 2k+1 pair up, then entry i of the 32 pair sums of
         // every wavefront sits in an LDS row that one lane adds up
@@ -408,7 +410,7 @@ __global__ __launch_bounds__(T) void k_ref_nodes(RefView R, double *cache, int8_
                 }
             }
             if (w == 0 && lane < CH && c0 + lane < NB)
-                cache[static_cast<int64_t>(slot_b<NP>(c0 + lane)) * nn + node] = tot;
+                cache[node * kNC + slot_b<NP>(c0 + lane)] = tot;
             __syncthreads();
         }
     }
@@ -429,8 +431,9 @@ __global__ __launch_bounds__(256) void k_ref_factor(RefView R, double *cache, in
     const int64_t nn = R.nodes;
     if (node >= nn || flag[node] < 0) return;
     const int N = R.N, h = (N - 1) / 2, n = N * N;
-    double *c = cache + node;
-    const double fm = c[0], S1 = c[1 * nn], S0 = c[2 * nn];
+    constexpr int kNC = 3 + 2 * NP + NH;
+    double *c = cache + node * kNC;
+    const double fm = c[0], S1 = c[1], S0 = c[2];
     // same expressions as the iteration's dg2 and J^T gbar, so that an
     // identical deformed subset gives a bitwise-zero increment
     const double gm = S0 * (1.0 / n);
@@ -438,10 +441,10 @@ __global__ __launch_bounds__(256) void k_ref_factor(RefView R, double *cache, in
     double SJ[NP];
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
-        SJ[a] = c[(3 + a) * nn];
-        c[(3 + NP + a) * nn] = c[(3 + NP + a) * nn] - gm * SJ[a];
+        SJ[a] = c[3 + a];
+        c[3 + NP + a] = c[3 + NP + a] - gm * SJ[a];
     }
-    c[1 * nn] = df2;
+    c[1] = df2;
     int8_t st = 0;
     const double lev = fmax(1.0, fabs(fm));
     if (isnan(df2)) st = kNan;
@@ -454,7 +457,7 @@ __global__ __launch_bounds__(256) void k_ref_factor(RefView R, double *cache, in
         for (int a = 0; a < NP; ++a)
 #pragma unroll
             for (int b = a; b < NP; ++b) {
-                Lm[tri(b, a)] = c[static_cast<int64_t>(3 + 2 * NP + q) * nn] - SJ[a] * SJ[b] / n;
+                Lm[tri(b, a)] = c[3 + 2 * NP + q] - SJ[a] * SJ[b] / n;
                 ++q;
             }
     }
@@ -507,7 +510,7 @@ __global__ __launch_bounds__(256) void k_ref_factor(RefView R, double *cache, in
             double x = 0.0;
 #pragma unroll
             for (int k = b; k < NP; ++k) x += Lm[tri(k, a)] * Lm[tri(k, b)];
-            c[static_cast<int64_t>(q++) * nn] = st == 0 ? x : 0.0;
+            c[q++] = st == 0 ? x : 0.0;
         }
     flag[node] = st;
 }
@@ -875,7 +878,7 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
                     (__attribute__((address_space(3))) void *)(qa), 4, 0, 0);
             }
         }
-        for (int q = t; q < NC; q += T) cache[q] = R.cache[static_cast<int64_t>(q) * nn + node];
+        for (int q = t; q < NC; q += T) cache[q] = R.cache[static_cast<int64_t>(node) * NC + q];
         if constexpr (kQaInLds) {
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();   // metadata visible to every wavefront
@@ -1314,6 +1317,7 @@ template <int LS, int P>
 __global__ __launch_bounds__(64) void k_ref_nodes_packed(RefView R, double *cache, int8_t *flag)
 {
     constexpr int NP = 6, NH = NP * (NP + 1) / 2, NB = NP + NH, G = 64 / LS;
+    constexpr int kNC = 3 + 2 * NP + NH;
     const int t = threadIdx.x, g = t / LS, tl = t - g * LS;
     const int N = R.N, h = (N - 1) / 2, n = N * N;
     const Columns L(tl, LS, N);
@@ -1369,13 +1373,14 @@ __global__ __launch_bounds__(64) void k_ref_nodes_packed(RefView R, double *cach
 #pragma unroll
         for (int i = 0; i < NB; ++i) vb[i] = seg_allreduce<LS>(vb[i]);
         if (valid && tl == 0) {
-            cache[node] = fm;
-            cache[1 * nn + node] = va[1];
-            cache[2 * nn + node] = va[0];
+            double *cn = cache + node * kNC;
+            cn[0] = fm;
+            cn[1] = va[1];
+            cn[2] = va[0];
 #pragma unroll
-            for (int a = 0; a < NP; ++a) cache[(3 + NP + a) * nn + node] = va[3 + a];
+            for (int a = 0; a < NP; ++a) cn[3 + NP + a] = va[3 + a];
 #pragma unroll
-            for (int i = 0; i < NB; ++i) cache[static_cast<int64_t>(slot_b<NP>(i)) * nn + node] = vb[i];
+            for (int i = 0; i < NB; ++i) cn[slot_b<NP>(i)] = vb[i];
         }
     }
 }
@@ -1451,7 +1456,7 @@ __global__ __launch_bounds__(64) void k_wave_packed(const FrameTable frames, int
         }
         __syncthreads();   // the previous slot is done with the LDS cache and windows
         if (act)
-            for (int q = tl; q < NC; q += LS) cache[g][q] = R.cache[static_cast<int64_t>(q) * nn + node];
+            for (int q = tl; q < NC; q += LS) cache[g][q] = R.cache[static_cast<int64_t>(node) * NC + q];
         float fb[P], gx[P], gy[P];
 #pragma unroll
         for (int j = 0; j < P; ++j) {
