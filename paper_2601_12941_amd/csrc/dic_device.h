@@ -147,6 +147,73 @@ __device__ __forceinline__ V wave_allreduce(V v)
     return v;
 }
 
+// After a permlane32 swap of (a, b), the sum of the two results is a(lane) + a(lane + 32)
+// on lanes 0-31 and b(lane - 32) + b(lane) on lanes 32-63;
+// the permlane16 form does the same for even and odd 16-lane rows.  One swap and one add
+// reduce two values over a lane pair, each kept by one side.
+__device__ __forceinline__ float swap_sum32(float a, float b)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_int(a), __float_as_int(b), false, false);
+    return __int_as_float(r[0]) + __int_as_float(r[1]);
+}
+__device__ __forceinline__ float swap_sum16(float a, float b)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(a), __float_as_int(b), false, false);
+    return __int_as_float(r[0]) + __int_as_float(r[1]);
+}
+__device__ __forceinline__ double swap_sum32(double a, double b)
+{
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+__device__ __forceinline__ double swap_sum16(double a, double b)
+{
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+__device__ __forceinline__ float read_lane(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
+__device__ __forceinline__ double read_lane(double v, int l)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l), __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// Sums over the 64 lanes of a wavefront of NV values at once, left in every lane as
+// uniform values.  Halves and then row pairs reduce the values two at a time (value
+// 2i kept by the lower half / even rows, 2i+1 by the upper half / odd rows; an odd one
+// out is summed on both sides), each 16-lane row then sums its remaining values with
+// the four row steps of wave_allreduce, and every total is read from a lane of the
+// class that holds it.  About a third of the instructions of NV separate all-reduces;
+// the order of the additions is fixed, so equal inputs give bitwise equal totals.
+template <int NV, typename V>
+__device__ __forceinline__ void wave_allreduce_n(V (&v)[NV])
+{
+    constexpr int N1 = (NV + 1) / 2, N2 = (N1 + 1) / 2;
+    V a[N1];
+#pragma unroll
+    for (int i = 0; i < NV / 2; ++i) a[i] = swap_sum32(v[2 * i], v[2 * i + 1]);
+    if constexpr (NV & 1) a[N1 - 1] = swap_sum32(v[NV - 1], v[NV - 1]);
+    V b[N2];
+#pragma unroll
+    for (int i = 0; i < N1 / 2; ++i) b[i] = swap_sum16(a[2 * i], a[2 * i + 1]);
+    if constexpr (N1 & 1) b[N2 - 1] = swap_sum16(a[N1 - 1], a[N1 - 1]);
+#pragma unroll
+    for (int i = 0; i < N2; ++i) {
+        b[i] += dpp_read<0xB1>(b[i]);
+        b[i] += dpp_read<0x4E>(b[i]);
+        b[i] += dpp_read<0x141>(b[i]);
+        b[i] += dpp_read<0x140>(b[i]);
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        // value k: step-1 slot k/2 on the half (k odd: upper), step-2 slot k/4 on the
+        // row parity (slot k/2 odd: odd rows)
+        const int lane = ((k & 1) ? 32 : 0) + (((k >> 1) & 1) ? 16 : 0);
+        v[k] = read_lane(b[k >> 2], lane);
+    }
+}
+
 // Degenerate-case thresholds: a subset is flat when its RMS deviation is below
 // 1e-6 of its mean level; a Cholesky pivot is singular below 1e-10 of the
 // largest Hessian diagonal, each entry taken in the units of the convergence

@@ -32,8 +32,8 @@ namespace dicmi {
 template <int T, int NV, typename V>
 __device__ __forceinline__ void block_allreduce(V (&v)[NV], V *red, int &parity)
 {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = wave_allreduce(v[i]);
+    if constexpr (NV == 1) v[0] = wave_allreduce(v[0]);
+    else wave_allreduce_n<NV>(v);
     if constexpr (T > 64) {
         constexpr int NW = T / 64;
         V *buf = red + parity * NW * NV;
@@ -60,8 +60,8 @@ __device__ __forceinline__ void block_allreduce(V (&v)[NV], V *red, int &parity)
 template <int T, int NV, typename V>
 __device__ __forceinline__ void block_reduce_first(V (&v)[NV], V *red, int &parity)
 {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = wave_allreduce(v[i]);
+    if constexpr (NV == 1) v[0] = wave_allreduce(v[0]);
+    else wave_allreduce_n<NV>(v);
     if constexpr (T > 64) {
         constexpr int NW = T / 64;
         V *buf = red + parity * NW * NV;
