@@ -27,19 +27,24 @@ namespace {
 
 constexpr int kVarT = 256;
 
-template <typename V> __device__ __forceinline__ void var_block_sum(V *v, int nv, double *red, double *out)
+template <int NV, typename V> __device__ __forceinline__ void var_block_sum(const V *v, double *red, double *out)
 {
-    // wavefront totals through the DPP/permlane all-reduce, then the 4
-    // wavefront partials summed in a fixed order; `out` (LDS) receives the sums
+    // wavefront totals (the values reduced together, as in the tuned kernel), then
+    // the 4 wavefront partials summed in a fixed order; `out` (LDS) receives the sums
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int i = 0; i < nv; ++i) {
-        const double tot = wave_allreduce(static_cast<double>(v[i]));
-        if (lane == 0) red[w * nv + i] = tot;
+    double d[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) d[i] = static_cast<double>(v[i]);
+    if constexpr (NV == 1) d[0] = wave_allreduce(d[0]);
+    else wave_allreduce_n<NV>(d);
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) red[w * NV + i] = d[i];
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < nv; i += kVarT) {
+    for (int i = threadIdx.x; i < NV; i += kVarT) {
         double acc = red[i];
-        for (int ww = 1; ww < kVarT / 64; ++ww) acc += red[ww * nv + i];
+        for (int ww = 1; ww < kVarT / 64; ++ww) acc += red[ww * NV + i];
         out[i] = acc;
     }
     __syncthreads();
@@ -198,7 +203,7 @@ __global__ __launch_bounds__(kVarT) void k_wave_var(const FrameTable frames, int
         {
             double sf = 0.0;
             for (int i = t; i < n; i += kVarT) sf += static_cast<double>(R.pf[obase + (i / N) * R.ppitch + i % N]);
-            var_block_sum(&sf, 1, red, sums);
+            var_block_sum<1>(&sf, red, sums);
         }
         if (t == 0) pub_fm = sums[0] / n;
         __syncthreads();
@@ -225,7 +230,7 @@ __global__ __launch_bounds__(kVarT) void k_wave_var(const FrameTable frames, int
                     v[2 + NP + NH + a] += J[a] * ft;
                 }
             }
-            var_block_sum(v, NR, red, sums);
+            var_block_sum<NR>(v, red, sums);
         }
         const double S0 = sums[0], S1 = sums[1];
         const double *SJ = sums + 2, *SJJ = sums + 2 + NP, *SJf = sums + 2 + NP + NH;
@@ -320,7 +325,7 @@ __global__ __launch_bounds__(kVarT) void k_wave_var(const FrameTable frames, int
                     zncc_out = 0.0f;
                     break;
                 }
-                var_block_sum(v, NI, red, isums);
+                var_block_sum<NI>(v, red, isums);
                 const double *I = isums;
                 if (t == 0) {
                     int stop = 0, st = kMaxIter;
