@@ -883,16 +883,24 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();   // metadata visible to every wavefront
         }
-        // reference intensities and gradients
+        // reference intensities and gradients: three pointers stepped by R rows (no
+        // per-row 64-bit multiply)
         float fb[P], gx[P], gy[P];
+        {
+            const int64_t o0 = static_cast<int64_t>(yc - h + L.r0) * R.ppitch + xc - h + L.c;
+            const int64_t rs = static_cast<int64_t>(L.R) * R.ppitch;
+            const float *af = R.pf + o0, *ax = R.pfx + o0, *ay = R.pfy + o0;
 #pragma unroll
-        for (int j = 0; j < P; ++j) {
-            fb[j] = gx[j] = gy[j] = 0.0f;
-            if (j < L.jmax) {
-                const int64_t o = static_cast<int64_t>(yc - h + L.r0 + L.R * j) * R.ppitch + xc - h + L.c;
-                fb[j] = R.pf[o];
-                gx[j] = R.pfx[o];
-                gy[j] = R.pfy[o];
+            for (int j = 0; j < P; ++j) {
+                fb[j] = gx[j] = gy[j] = 0.0f;
+                if (j < L.jmax) {
+                    fb[j] = *af;
+                    gx[j] = *ax;
+                    gy[j] = *ay;
+                }
+                af += rs;
+                ax += rs;
+                ay += rs;
             }
         }
         if constexpr (!kQaInLds) __syncthreads();   // cache visible to every wavefront
@@ -1008,25 +1016,28 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
                     if (!half) {
                         // each wavefront fills 64 consecutive window elements per request,
                         // straight into LDS (no registers, all requests in flight at once)
+                        // the source pointer steps with the element: dr rows and dc
+                        // columns per request, one more row when the column wraps
                         const float *g = static_cast<const float *>(F.dcoef);
                         const int lane = t & 63;
                         const int e_first = (t & ~63);
                         int e = e_first + lane;
-                        int r = e / ts, c = e - (e / ts) * ts;
+                        int c = e - (e / ts) * ts;
                         const int dr = T / ts, dc = T - (T / ts) * ts;
+                        const int64_t dpitch = F.dpitch;
+                        const float *src = g + static_cast<int64_t>(oy + e / ts) * dpitch + (ox + c);
+                        const int64_t step_a = dr * dpitch + dc, step_b = dpitch - ts;
                         for (int e0 = e_first; e0 < ts * ts; e0 += T) {
-                            if (e < ts * ts) {
-                                const float *src = g + static_cast<int64_t>(oy + r) * F.dpitch + (ox + c);
+                            if (e < ts * ts)
                                 __builtin_amdgcn_global_load_lds(
                                     (const __attribute__((address_space(1))) void *)(src),
                                     (__attribute__((address_space(3))) void *)(tile + e0), 4, 0, 0);
-                            }
                             e += T;
-                            r += dr;
                             c += dc;
+                            src += step_a;
                             if (c >= ts) {
                                 c -= ts;
-                                ++r;
+                                src += step_b;
                             }
                         }
                         __builtin_amdgcn_s_waitcnt(0);
@@ -1458,14 +1469,21 @@ __global__ __launch_bounds__(64) void k_wave_packed(const FrameTable frames, int
         if (act)
             for (int q = tl; q < NC; q += LS) cache[g][q] = R.cache[static_cast<int64_t>(node) * NC + q];
         float fb[P], gx[P], gy[P];
+        {
+            const int64_t o0 = static_cast<int64_t>(yc - h + L.r0) * R.ppitch + xc - h + L.c;
+            const int64_t rs = static_cast<int64_t>(L.R) * R.ppitch;
+            const float *af = R.pf + o0, *ax = R.pfx + o0, *ay = R.pfy + o0;
 #pragma unroll
-        for (int j = 0; j < P; ++j) {
-            fb[j] = gx[j] = gy[j] = 0.0f;
-            if (act && j < L.jmax) {
-                const int64_t o = static_cast<int64_t>(yc - h + L.r0 + L.R * j) * R.ppitch + xc - h + L.c;
-                fb[j] = R.pf[o];
-                gx[j] = R.pfx[o];
-                gy[j] = R.pfy[o];
+            for (int j = 0; j < P; ++j) {
+                fb[j] = gx[j] = gy[j] = 0.0f;
+                if (act && j < L.jmax) {
+                    fb[j] = *af;
+                    gx[j] = *ax;
+                    gy[j] = *ay;
+                }
+                af += rs;
+                ax += rs;
+                ay += rs;
             }
         }
         double p[NP];
