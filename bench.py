@@ -259,6 +259,51 @@ def summarize_pmc(fetch_dir, write_dir, cfetch_dir, cwrite_dir, out_md, out_json
     print("wrote", out_md, out_json)
 
 
+def summarize_l2(bench_dir, copy_dir, trace_dir, out_md):
+    """profiles/k_wave_2048_l2_counters.md: L2 (TCC) read requests, hits and misses per
+    dispatch of the batched k_wave, the request size calibrated on the 256 MiB copy, and
+    the rate over the launch time of a kernel trace of the same build."""
+    import csv
+
+    def per_kernel(d):
+        f = next(os.path.join(r, x) for r, _, fs in os.walk(d) for x in fs if x.endswith("counter_collection.csv"))
+        acc, disp = {}, {}
+        for r in csv.DictReader(open(f)):
+            k = (_short(r["Kernel_Name"]), r["Counter_Name"])
+            acc[k] = acc.get(k, 0.0) + float(r["Counter_Value"])
+            disp.setdefault(k, set()).add(r["Dispatch_Id"])
+        return {k: (acc[k] / len(disp[k]), len(disp[k])) for k in acc}
+    b, c = per_kernel(bench_dir), per_kernel(copy_dir)
+    copy_reads = max(v[0] for k, v in c.items() if k[1] == "TCC_READ_sum")
+    req_b = 256 * (1 << 20) / copy_reads
+    kb = "k_wave<6, 64, 16, true>"
+    rd, n = b[(kb, "TCC_READ_sum")]
+    hit, miss = b[(kb, "TCC_HIT_sum")][0], b[(kb, "TCC_MISS_sum")][0]
+    stats = next(os.path.join(r, f) for r, _, fs in os.walk(trace_dir) for f in fs if f.endswith("kernel_stats.csv"))
+    avg_us = next(float(r["AverageNs"]) / 1e3 for r in csv.DictReader(open(stats)) if _short(r["Name"]) == kb)
+    from paper_2601_12941_amd import build
+    lines = ["# k_wave on the 2048^2 workload: L2 (TCC) counters", "",
+             "Commands (each a separate pass; rocprofv3 run from /tmp with TMPDIR=/tmp, from the repository root "
+             "on the MI355X box):", "", "```",
+             "rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum TCC_READ_sum -f csv -d <bench> -o run -- python3 " + PMC_BENCH,
+             "rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum TCC_READ_sum -f csv -d <copy> -o run -- python3 bench.py "
+             "--copy-probe", "```", "",
+             "Summary written by `python bench.py --summarize-l2 <bench> <copy> <trace>` (<trace>: the kernel trace "
+             "of `k_wave_2048_kernel_trace.md`, for the launch time).", "",
+             "Calibration: the 256 MiB device copy issues %.0f TCC read requests per dispatch, i.e. %.1f B per "
+             "request (one 128 B line)." % (copy_reads, req_b), "",
+             "| Kernel | Dispatches | TCC_READ_sum / dispatch | L2 read bytes / dispatch | TCC_HIT_sum | TCC_MISS_sum "
+             "| hit rate |", "|---|---|---|---|---|---|---|",
+             "| `%s` (batched, 16 frames) | %d | %.0f | %.0f MB | %.0f | %.0f | %.1f %% |" % (
+                 kb, n, rd, rd * 128 / 1e6, hit, miss, 100.0 * hit / max(1.0, hit + miss)), "",
+             "Over the batched launch's %.1f us (kernel trace of the same build) that is %.1f TB/s of L2 reads; the "
+             "achievable L2 re-read rate measured by `dic_roof_cache_read` is 32.6 TB/s "
+             "(`achievable_rates_mi355x.md`)." % (avg_us, rd * 128 / (avg_us * 1e-6) / 1e12), "",
+             "Kernel build at the time of these counters: sha256 `%s`." % build.kernel_build_id()]
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    print("wrote", out_md)
+
+
 def copy_probe(mib=256, reps=3):
     """A device-to-device copy of known size: its FETCH_SIZE / WRITE_SIZE counters
     read `mib` MiB each per dispatch on an exact counter."""
@@ -891,6 +936,8 @@ def main():
     ap.add_argument("--parity-samples", type=int, default=8, help="serve: requests checked against the oracle")
     ap.add_argument("--summarize-trace", metavar="DIR", help="write the kernel-trace summary of a rocprofv3 run")
     ap.add_argument("--summary-out", default=os.path.join(ROOT, "profiles", "k_wave_2048_kernel_trace.md"))
+    ap.add_argument("--summarize-l2", nargs=3, metavar=("BENCH", "COPY", "TRACE"),
+                    help="write the L2 counter summary from two rocprofv3 --pmc runs and a kernel trace")
     ap.add_argument("--summarize-ext-trace", metavar="DIR",
                     help="write the kernel-trace summary of a profiled --workload extensions run")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
@@ -901,6 +948,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, args.summary_out)
+        return
+    if args.summarize_l2:
+        summarize_l2(*args.summarize_l2, os.path.join(ROOT, "profiles", "k_wave_2048_l2_counters.md"))
         return
     if args.summarize_ext_trace:
         summarize_ext_trace(args.summarize_ext_trace, args.summary_out)
