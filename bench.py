@@ -304,6 +304,50 @@ def summarize_l2(bench_dir, copy_dir, trace_dir, out_md):
     print("wrote", out_md)
 
 
+SQ_COUNTERS = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_BUSY_CYCLES"]
+
+
+def summarize_sq(sq_dir, trace_dir, out_md):
+    """profiles/k_wave_2048_sq_counters.md: instructions per subset of the batched
+    k_wave (one wavefront per subset at 64 threads) from one rocprofv3 --pmc pass, and
+    the VALU issue rate over the launch time of a kernel trace of the same build."""
+    import csv
+    f = next(os.path.join(r, x) for r, _, fs in os.walk(sq_dir) for x in fs if x.endswith("counter_collection.csv"))
+    acc, disp = {}, {}
+    for r in csv.DictReader(open(f)):
+        k = (_short(r["Kernel_Name"]), r["Counter_Name"])
+        acc[k] = acc.get(k, 0.0) + float(r["Counter_Value"])
+        disp.setdefault(k, set()).add(r["Dispatch_Id"])
+    kb = "k_wave<6, 64, 16, true>"
+    v = {c: acc[(kb, c)] / len(disp[(kb, c)]) for c in SQ_COUNTERS if (kb, c) in acc}
+    n = len(disp[(kb, "SQ_WAVES")])
+    stats = next(os.path.join(r, x) for r, _, fs in os.walk(trace_dir) for x in fs if x.endswith("kernel_stats.csv"))
+    avg_us = next(float(r["AverageNs"]) / 1e3 for r in csv.DictReader(open(stats)) if _short(r["Name"]) == kb)
+    # workgroups that find no subset exit at once: the subsets of a launch are the
+    # converged subsets the benchmark counts (15 843.5 per launch on this workload)
+    subsets = 1010025 * 16 / 1020.0
+    issue = v["SQ_INSTS_VALU"] / (avg_us * 1e-6)
+    simd_rate = 256 * 4 * 2.4e9 / 4          # one wave64 VALU instruction per SIMD every 4 clocks
+    from paper_2601_12941_amd import build
+    lines = ["# k_wave on the 2048^2 workload: SQ instruction counters", "",
+             "Command (rocprofv3 run from /tmp with TMPDIR=/tmp, from the repository root on the MI355X box):", "",
+             "```", "rocprofv3 --pmc " + " ".join(SQ_COUNTERS) + " -f csv -d <sq> -o run -- python3 " + PMC_BENCH,
+             "```", "",
+             "Summary written by `python bench.py --summarize-sq <sq> <trace>` (<trace>: the kernel trace of "
+             "`k_wave_2048_kernel_trace.md`, for the launch time).", "",
+             "| Counter | per dispatch of `%s` (%d dispatches) | per subset |" % (kb, n), "|---|---|---|"]
+    for c in SQ_COUNTERS:
+        if c in v:
+            lines.append("| `%s` | %.0f | %.1f |" % (c, v[c], v[c] / subsets))
+    lines += ["", "Subsets per launch: %.1f (1 010 025 per frame, 16 frames, 1020 launches per step)." % subsets,
+              "VALU issue over the %.1f us launch (kernel trace of the same build): %.2e instructions/s, %.0f %% of "
+              "the %.2e that 1024 SIMDs issue at one wave64 instruction every 4 clocks (2.4 GHz)." % (
+                  avg_us, issue, 100.0 * issue / simd_rate, simd_rate), "",
+              "Kernel build at the time of these counters: sha256 `%s`." % build.kernel_build_id()]
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    print("wrote", out_md)
+
+
 def copy_probe(mib=256, reps=3):
     """A device-to-device copy of known size: its FETCH_SIZE / WRITE_SIZE counters
     read `mib` MiB each per dispatch on an exact counter."""
@@ -936,6 +980,8 @@ def main():
     ap.add_argument("--parity-samples", type=int, default=8, help="serve: requests checked against the oracle")
     ap.add_argument("--summarize-trace", metavar="DIR", help="write the kernel-trace summary of a rocprofv3 run")
     ap.add_argument("--summary-out", default=os.path.join(ROOT, "profiles", "k_wave_2048_kernel_trace.md"))
+    ap.add_argument("--summarize-sq", nargs=2, metavar=("SQ", "TRACE"),
+                    help="write the SQ instruction-counter summary from a rocprofv3 --pmc run and a kernel trace")
     ap.add_argument("--summarize-l2", nargs=3, metavar=("BENCH", "COPY", "TRACE"),
                     help="write the L2 counter summary from two rocprofv3 --pmc runs and a kernel trace")
     ap.add_argument("--summarize-ext-trace", metavar="DIR",
@@ -948,6 +994,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, args.summary_out)
+        return
+    if args.summarize_sq:
+        summarize_sq(*args.summarize_sq, os.path.join(ROOT, "profiles", "k_wave_2048_sq_counters.md"))
         return
     if args.summarize_l2:
         summarize_l2(*args.summarize_l2, os.path.join(ROOT, "profiles", "k_wave_2048_l2_counters.md"))
