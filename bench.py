@@ -337,8 +337,9 @@ def summarize_sq(sq_dir, trace_dir, out_md):
              "`k_wave_2048_kernel_trace.md`, for the launch time).", "",
              "| Counter | per dispatch of `%s` (%d dispatches) | per subset |" % (kb, n), "|---|---|---|"]
     for c in SQ_COUNTERS:
-        if c in v:
-            lines.append("| `%s` | %.0f | %.1f |" % (c, v[c], v[c] / subsets))
+        if c in v:   # wavefronts and busy cycles are per launch, not per subset
+            per = "" if c in ("SQ_WAVES", "SQ_BUSY_CYCLES") else "%.1f" % (v[c] / subsets)
+            lines.append("| `%s` | %.0f | %s |" % (c, v[c], per))
     lines += ["", "Subsets per launch: %.1f (1 010 025 per frame, 16 frames, 1020 launches per step)." % subsets,
               "VALU issue over the %.1f us launch (kernel trace of the same build): %.2e instructions/s, %.0f %% of "
               "the %.2e that 1024 SIMDs issue at one wave64 instruction every 4 clocks (2.4 GHz)." % (
