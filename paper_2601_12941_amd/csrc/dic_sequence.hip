@@ -116,6 +116,7 @@ __global__ void k_seq_accumulate(SeqResult ref, int has_ref, SeqResult inc, SeqR
     }
     const double x = static_cast<double>(h + i * step) + ur, y = static_cast<double>(h + j * step) + vr;
     const double fx = (x - h) / step, fy = (y - h) / step;
+    if (!isfinite(fx) || !isfinite(fy)) return;   // not reached (a reference state with no number)
     const double fi0 = floor(fx), fj0 = floor(fy);
     const double ax = fx - fi0, ay = fy - fj0;
     // the cell's far column / row is needed only where it carries weight
