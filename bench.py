@@ -11,8 +11,7 @@ search, every frontier wave of IC-GN, output) over a batch of B deformed
 frames of that pair against the resident reference; `value` is converged
 subsets per second over the K timed steps.  The plain (one frame per call)
 engine is timed beside it, with its p50/p99 pair latency.  The two forms use
-their own launch shapes (threads per subset: 64 for the batched form, which
-is throughput-bound; 128 for the plain form, which is latency-bound).
+their own launch shapes, each picked by the autotuner on the workload itself.
 
 Prints one JSON line.
 """
@@ -160,7 +159,7 @@ def summarize_trace(d, out):
              "```", "rocprofv3 --kernel-trace --stats -f csv -d <out> -o run -- python3 " + PROFILE_BENCH, "```", "",
              "Summary written by `python bench.py --summarize-trace <out> --summary-out <this file>`.", "",
              "Workload: 2048x2048 u16 speckle, sinusoidal u, subset 31, step 2, affine (1 010 025 active subsets per "
-             "frame, 1005 waves). Batched form: 16 frames per launch, %d threads per subset, %d-sample window "
+             "frame, 1005 waves). Batched form: 32 frames per launch, %d threads per subset, %d-sample window "
              "(the autotuner's pick on this workload); plain form: one frame per call, %d threads per subset, "
              "%d-sample window (64 and 128 threads tie within 1%% for the plain form)." % (
                  PROFILE_SHAPES["tps"], PROFILE_SHAPES["tile"], PROFILE_SHAPES["plain_tps"],
@@ -251,7 +250,7 @@ def summarize_pmc(fetch_dir, write_dir, cfetch_dir, cwrite_dir, out_md, out_json
     write_b = wr[kb][0] * 1024 * wf
     lines += ["", "Kernel build at the time of these counters: sha256 `%s` of the source and its compile flags." % kid]
     open(out_md, "w").write("\n".join(lines) + "\n")
-    json.dump({"kernel": kb + " (batched form, 16 frames per launch)", "kernel_build_sha256": kid,
+    json.dump({"kernel": kb + " (batched form, 32 frames per launch)", "kernel_build_sha256": kid,
                "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
                "traffic_bytes_per_launch": fetch_b + write_b, "dispatches": fe[kb][1],
                "copy_calibration": {"bytes": copy_bytes, "fetch_kib": cf, "write_kib": cw, "fetch_factor": ff,
@@ -294,7 +293,7 @@ def summarize_l2(bench_dir, copy_dir, trace_dir, out_md):
              "request (one 128 B line)." % (copy_reads, req_b), "",
              "| Kernel | Dispatches | TCC_READ_sum / dispatch | L2 read bytes / dispatch | TCC_HIT_sum | TCC_MISS_sum "
              "| hit rate |", "|---|---|---|---|---|---|---|",
-             "| `%s` (batched, 16 frames) | %d | %.0f | %.0f MB | %.0f | %.0f | %.1f %% |" % (
+             "| `%s` (batched, 32 frames) | %d | %.0f | %.0f MB | %.0f | %.0f | %.1f %% |" % (
                  kb, n, rd, rd * 128 / 1e6, hit, miss, 100.0 * hit / max(1.0, hit + miss)), "",
              "Over the batched launch's %.1f us (kernel trace of the same build) that is %.1f TB/s of L2 reads; the "
              "achievable L2 re-read rate measured by `dic_roof_cache_read` is 32.6 TB/s "
@@ -324,8 +323,8 @@ def summarize_sq(sq_dir, trace_dir, out_md):
     stats = next(os.path.join(r, x) for r, _, fs in os.walk(trace_dir) for x in fs if x.endswith("kernel_stats.csv"))
     avg_us = next(float(r["AverageNs"]) / 1e3 for r in csv.DictReader(open(stats)) if _short(r["Name"]) == kb)
     # workgroups that find no subset exit at once: the subsets of a launch are the
-    # converged subsets the benchmark counts (15 843.5 per launch on this workload)
-    subsets = 1010025 * 16 / 1020.0
+    # converged subsets the benchmark counts (31 687 per launch on this workload)
+    subsets = 1010025 * 32 / 1020.0
     issue = v["SQ_INSTS_VALU"] / (avg_us * 1e-6)
     simd_rate = 256 * 4 * 2.4e9 / 4          # one wave64 VALU instruction per SIMD every 4 clocks
     from paper_2601_12941_amd import build
@@ -340,7 +339,7 @@ def summarize_sq(sq_dir, trace_dir, out_md):
         if c in v:   # wavefronts and busy cycles are per launch, not per subset
             per = "" if c in ("SQ_WAVES", "SQ_BUSY_CYCLES") else "%.1f" % (v[c] / subsets)
             lines.append("| `%s` | %.0f | %s |" % (c, v[c], per))
-    lines += ["", "Subsets per launch: %.1f (1 010 025 per frame, 16 frames, 1020 launches per step)." % subsets,
+    lines += ["", "Subsets per launch: %.1f (1 010 025 per frame, 32 frames, 1020 launches per step)." % subsets,
               "VALU issue over the %.1f us launch (kernel trace of the same build): %.2e instructions/s, %.0f %% of "
               "the %.2e that 1024 SIMDs issue at one wave64 instruction every 4 clocks (2.4 GHz)." % (
                   avg_us, issue, 100.0 * issue / simd_rate, simd_rate), "",
@@ -949,7 +948,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=16, help="deformed frames per batched step")
+    ap.add_argument("--batch", type=int, default=32, help="deformed frames per batched step (at most 32)")
     ap.add_argument("--latency-runs", type=int, default=60, help="plain single-frame calls for p50/p99")
     ap.add_argument("--size", type=int, default=2048)
     ap.add_argument("--fp32-reductions", action="store_true")
@@ -1160,7 +1159,7 @@ def main():
     avg_launch_ms = kern_ms / max(1, launches)
     achieved = flops / (kern_ms * 1e-3) / 1e12
     # the committed counters describe the profiled launch shape only
-    profiled = (args.batch == 16 and args.size == 2048 and last["threads_per_subset"] == PROFILE_SHAPES["tps"]
+    profiled = (args.batch == 32 and args.size == 2048 and last["threads_per_subset"] == PROFILE_SHAPES["tps"]
                 and tile_b == PROFILE_SHAPES["tile"] and not args.fp32_reductions)
     traffic = profiled_traffic() if profiled else None
     roofline = {"bound": "alu", "kernel": "k_wave (IC-GN frontier wave)", "achieved": achieved,

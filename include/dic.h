@@ -204,7 +204,8 @@ dic_status dic_correlate(dic_ctx *c, const dic_image *def, const dic_seed *seeds
  * Correlate `nframes` deformed images against the same reference in one
  * batched pass: every frontier wave of every frame goes into one launch.
  * seeds: nframes * nseeds host seeds (frame-major); outs: nframes results.
- * Each frame's results equal those of dic_correlate on that frame alone.
+ * 1 <= nframes <= 32 (DIC_E_INVAL otherwise).  Each frame's results equal
+ * those of dic_correlate on that frame alone.
  */
 dic_status dic_correlate_batch(dic_ctx *c, const dic_image *defs, int32_t nframes, const dic_seed *seeds,
                                int32_t nseeds, dic_result *outs);

@@ -336,7 +336,7 @@ __device__ __forceinline__ void compose_quadratic(double (&p)[12], const double 
 // wave raises the child's parent key to (ordered ZNCC << 2 | priority), where
 // the priority 3, 2, 1, 0 says that the child sees this node on its left,
 // right, above or below: the exact-tie order of the parent rule.
-__device__ __forceinline__ void push_children(const FrameState &F, const RefView &R, int ix, int iy, int k,
+__device__ __forceinline__ void push_children(const WaveFrame &F, const RefView &R, int ix, int iy, int k,
                                               float zncc, int32_t *lout, int t)
 {
     int64_t m = -1;

@@ -13,7 +13,7 @@ namespace dicmi {
 constexpr int kPad = 4;
 // Frames one batched launch may carry (the frame table travels in the kernel
 // arguments, which hold at most 4 KiB).
-constexpr int kMaxFrames = 16;
+constexpr int kMaxFrames = 32;
 
 enum NodeStatus : int8_t {
     kConverged = 0,
@@ -85,12 +85,41 @@ struct FrameState {
     int kmax;             // last valid index of counts (nodes + 1)
 };
 
+// What a wave kernel reads of a frame (FrameState without the raw image and the
+// seed list, which only the seed search reads): 120 bytes, so that 32 frames fit
+// the 4 KiB of kernel arguments.
+struct WaveFrame {
+    const void *dcoef;
+    int64_t dpitch;
+    float *p;
+    float *zncc;
+    int16_t *iters;
+    int8_t *status;
+    int32_t *wave;
+    uint64_t *pkey;
+    int32_t *list0, *list1;
+    int32_t *counts;
+    double *seed_p;
+    unsigned long long *stat;
+    const RefView *ref;
+    int k_base;
+    int kmax;
+    WaveFrame() = default;
+    WaveFrame(const FrameState &F)
+        : dcoef(F.dcoef), dpitch(F.dpitch), p(F.p), zncc(F.zncc), iters(F.iters), status(F.status), wave(F.wave),
+          pkey(F.pkey), list0(F.list0), list1(F.list1), counts(F.counts), seed_p(F.seed_p), stat(F.stat),
+          ref(F.ref), k_base(F.k_base), kmax(F.kmax)
+    {
+    }
+};
+
 // The frames of one launch, passed by value as a kernel argument: uniform
 // indexing gives scalar loads, and the pointers are known to be global.
 struct FrameTable {
-    FrameState f[kMaxFrames];
+    WaveFrame f[kMaxFrames];
     int n;
 };
+static_assert(sizeof(FrameTable) + sizeof(int) <= 4096, "the frame table must fit the kernel arguments");
 
 // ---- launchers (dic_kernels.hip) -------------------------------------
 void launch_prefilter(const void *src, int64_t src_pitch_bytes, int pixel, int W, int H, float *tmp,

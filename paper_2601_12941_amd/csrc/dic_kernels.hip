@@ -826,7 +826,7 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
         while (m + 1 < nown && prefix[m + 1] <= gi) ++m;
         m = __builtin_amdgcn_readfirstlane(m);
         const int f = __builtin_amdgcn_readfirstlane(owned[m]);
-        const FrameState &F = frames.f[f];
+        const WaveFrame &F = frames.f[f];
         const RefView R = *F.ref;                 // this frame's reference (uniform loads)
         const int k = step - F.k_base;            // this frame's wave
         const int ts = R.ts, half = R.half;
@@ -1435,7 +1435,7 @@ __global__ __launch_bounds__(64) void k_wave_packed(const FrameTable frames, int
         while (m + 1 < nown && prefix[m + 1] <= si) ++m;
         m = __builtin_amdgcn_readfirstlane(m);
         const int f = __builtin_amdgcn_readfirstlane(owned[m]);
-        const FrameState &F = frames.f[f];
+        const WaveFrame &F = frames.f[f];
         const RefView R = *F.ref;
         const int k = step - F.k_base;
         const int ts = R.ts, half = R.half;
@@ -1832,8 +1832,11 @@ int wave_grid_hint(int np, int tps, int device)
 {
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-    // enough workgroups to keep every SIMD busy with a few subsets each
-    const int per_cu = tps <= 64 ? 16 : (tps == 128 ? 8 : 4);
+    // enough workgroups to keep every SIMD busy; one-wavefront workgroups take about
+    // two subsets each of a full 32-frame wave, so their uneven run times even out over
+    // many workgroups (64 per compute unit: +2.4 % over 16 with 16 frames per launch,
+    // +2.5 % over 32 with 32 frames; 128 is no faster)
+    const int per_cu = tps <= 64 ? 64 : (tps == 128 ? 8 : 4);
     (void)np;
     return cus * per_cu;
 }

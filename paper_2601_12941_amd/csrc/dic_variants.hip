@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kVarT) void k_wave_var(const FrameTable frames, int
         int m = 0;
         while (m + 1 < nframes && prefix[m + 1] <= gi) ++m;
         m = __builtin_amdgcn_readfirstlane(m);
-        const FrameState &F = frames.f[m];
+        const WaveFrame &F = frames.f[m];
         const RefView R = *F.ref;
         const int k = step - F.k_base;
         const int N = R.N, h = (N - 1) / 2, n = N * N;

@@ -62,9 +62,9 @@ def test_repeat_runs_are_bitwise_identical(c1):
         assert np.array_equal(a[k], b[k]), k
 
 
-@pytest.mark.parametrize("nframes", [3, 8, 16])
+@pytest.mark.parametrize("nframes", [3, 8, 16, 32])
 def test_batch_equals_plain(nframes):
-    # 8 and 16 frames take the kernel's frame-to-XCD affinity (every 8th frame on
+    # 8, 16 and 32 frames take the kernel's frame-to-XCD affinity (every 8th frame on
     # one XCD group), 3 frames the plain grid stride; both must give every frame
     # bitwise the results of its own plain call
     import torch
@@ -79,3 +79,17 @@ def test_batch_equals_plain(nframes):
     for a, b in zip(plain, batch):
         for k in a:
             assert torch.equal(a[k], b[k]), k
+
+
+def test_batch_frame_limit():
+    import torch
+    from paper_2601_12941_amd import dic
+    w = synth.workload("c1", size=128)
+    pair = w.pair()
+    eng = dic.Engine(0)
+    eng.set_reference(dic.to_device_image(pair.ref), torch.from_numpy(pair.roi).cuda(), **w.params())
+    d = dic.to_device_image(pair.deformed)
+    with pytest.raises(dic.DicError) as e:
+        eng.correlate_batch([d] * 33, w.seeds)
+    assert e.value.code == dic.DIC_E_INVAL
+    eng.close()
