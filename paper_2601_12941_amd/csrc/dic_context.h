@@ -140,6 +140,8 @@ struct dic_ctx {
         R.guess_copy = prm.guess_mode;
         R.half = prm.coef_fp16 != 0;
         R.ts = window_side();
+        R.lp = lds_pitch(prm.subset_size, R.ts);
+        R.inv_n = 1.0 / (static_cast<double>(prm.subset_size) * prm.subset_size);
         R.cost = prm.cost;
         R.lm_lambda = prm.lm_lambda;
         return R;

@@ -161,6 +161,12 @@ dic_status dic_set_reference(dic_ctx *c, const dic_image *ref, const uint8_t *ro
         FAIL(DIC_E_UNSUPPORTED, "packed subsets (%d threads per subset) are built for the affine shape", tps);
     if (!variant && p.shape == DIC_SHAPE_QUADRATIC && tps == 64 && p.subset_size > 21)
         FAIL(DIC_E_UNSUPPORTED, "quadratic shape with 64 threads is built for subsets up to 21");
+    {
+        const int64_t cp = round_up(ref->width + 2 * kPad, 64);
+        const int ts = p.tile_side ? p.tile_side : tile_side(p.subset_size);
+        if (!window_offsets_fit(cp, ts))
+            FAIL(DIC_E_INVAL, "image width %d with a %d-sample window: window offsets exceed 32 bits", ref->width, ts);
+    }
 
     HIPCHK(hipSetDevice(c->device));
     HIPCHK(c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize());
@@ -345,7 +351,7 @@ dic_status run_frames(dic_ctx *c, const dic_image *defs, int nframes, int nseeds
         }
         for (int j = 0; j < chunk && k <= c->nodes; ++j, ++k)
             if (c->variant ? !launch_wave_var(table, k, c->np, grid, s)
-                           : !launch_wave(table, k, c->np, c->prm.subset_size, c->tps, f64, R.ts, grid, s))
+                           : !launch_wave(table, k, c->np, c->prm.subset_size, c->tps, f64, R.ts, R.ts * R.lp, grid, s))
                 FAIL(DIC_E_UNSUPPORTED, "no kernel for shape %d, %d threads, subset %d", c->np, c->tps,
                      c->prm.subset_size);
         HIPCHK(hipGetLastError());

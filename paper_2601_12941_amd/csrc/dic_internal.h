@@ -11,6 +11,24 @@ namespace dicmi {
 // Coefficient arrays carry this many mirrored samples on every side, so that
 // the 4x4 taps of any in-image point (x0-1 .. x0+2) never need index folding.
 constexpr int kPad = 4;
+// Fourth word of a raw buffer descriptor on this GPU family (32-bit data format,
+// no swizzle); with stride 0 the descriptor is a plain byte-addressed view.
+constexpr int kBufferWord3 = 0x00020000;
+// The wave kernels stage a coefficient window with 32-bit byte offsets from its
+// origin, so the window side times the coefficient row pitch, in bytes, must stay
+// below 2^31.
+// Row pitch of the LDS coefficient window: the smallest value >= the window side
+// congruent to the subset size N modulo 32.  Thread i of a subset reads column
+// i mod N of subset row i div N, so with this pitch the threads of a wavefront
+// over an untransformed subset fall on consecutive LDS banks (a quarter fewer
+// bank conflicts than with the window side as pitch; modulo 64 measured the
+// same).  Windows whose padded size would pass 32 KiB keep the unpadded pitch.
+inline int lds_pitch(int N, int ts)
+{
+    const int lp = ts + (((N - ts) % 32) + 32) % 32;
+    return lp * ts <= 8192 ? lp : ts;
+}
+inline bool window_offsets_fit(int64_t cpitch, int ts) { return 4 * cpitch * ts <= 0x7fffffffLL; }
 // Frames one batched launch may carry (the frame table travels in the kernel
 // arguments, which hold at most 4 KiB).
 constexpr int kMaxFrames = 32;
@@ -57,6 +75,8 @@ struct RefView {
     int guess_copy;      // 1: copy the neighbour's p, 0: extrapolate
     int half;            // deformed coefficients stored as FP16
     int ts;              // side of the LDS coefficient window
+    int lp;              // LDS row pitch of that window (lds_pitch(N, ts))
+    double inv_n;        // 1 / (N * N), correctly rounded
     int cost;            // 0 ZNSSD (Eq. (4)), 1 NSSD (Eq. (3)), 2 SSD (Eq. (2)); the variant kernel only
     double lm_lambda;    // initial Levenberg-Marquardt damping (0: Gauss-Newton); the variant kernel only
 };
@@ -132,8 +152,10 @@ void launch_seed_search(const RefView &R, const FrameState *F_dev, int nframes, 
                         const int32_t *seed_center_dev, double *zbuf, hipStream_t s);
 void launch_seed_pick(const RefView &R, const FrameState *F_dev, int nframes, int nseeds, int radius,
                       const int32_t *seed_center_dev, const double *zbuf, hipStream_t s);
-bool launch_wave(const FrameTable &F, int step, int np, int N, int tps, bool f64, int max_ts, int grid,
-                 hipStream_t s);
+// max_ts: the largest window side of the launch's frames; lds_floats: the largest
+// window footprint in LDS (side times lds_pitch) among them
+bool launch_wave(const FrameTable &F, int step, int np, int N, int tps, bool f64, int max_ts, int lds_floats,
+                 int grid, hipStream_t s);
 void launch_gather_next(const FrameState *F_dev, int n, int step, int32_t *out, hipStream_t s);
 void launch_frame_stats(const RefView &R, const FrameState &F, hipStream_t s);
 void launch_count_wave(const FrameState *F_dev, int nframes, int k, int32_t *out, hipStream_t s);

@@ -829,9 +829,9 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
         const WaveFrame &F = frames.f[f];
         const RefView R = *F.ref;                 // this frame's reference (uniform loads)
         const int k = step - F.k_base;            // this frame's wave
-        const int ts = R.ts, half = R.half;
+        const int ts = R.ts, lp = R.lp, half = R.half;
         const int N = R.N, h = (N - 1) / 2, n = N * N;
-        const double inv_n = 1.0 / n;
+        const double inv_n = R.inv_n;
         const int64_t nn = R.nodes;
         const Columns L(t, T, N);
         const float dxf = static_cast<float>(L.c - h);
@@ -883,24 +883,42 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();   // metadata visible to every wavefront
         }
-        // reference intensities and gradients: three pointers stepped by R rows (no
-        // per-row 64-bit multiply)
+        // rows per thread of this subset (a launch may mix subset sizes, P is the
+        // largest); uniform across the workgroup
+        const int JM = __builtin_amdgcn_readfirstlane((N + L.R - 1) / L.R);
+        // reference intensities and gradients.  Row j of every thread lies at the
+        // uniform address of subset row R j plus a fixed per-thread byte offset, so
+        // the loads take a scalar base and no vector address arithmetic.  Threads past
+        // the subset's rows (the last row of some threads, all rows of the spare
+        // threads) read a row inside the subset instead; the pixel loop weights those
+        // entries by zero.
         float fb[P], gx[P], gy[P];
         {
-            const int64_t o0 = static_cast<int64_t>(yc - h + L.r0) * R.ppitch + xc - h + L.c;
-            const int64_t rs = static_cast<int64_t>(L.R) * R.ppitch;
-            const float *af = R.pf + o0, *ax = R.pfx + o0, *ay = R.pfy + o0;
+            const int64_t top = static_cast<int64_t>(yc - h) * R.ppitch + (xc - h);
+            const int rown = L.jmax > 0 ? L.r0 : 0;
+            const int rlast = min(rown + L.R * (JM - 1), N - 1) - L.R * (JM - 1);
+            const int lo = 4 * (rown * static_cast<int>(R.ppitch) + L.c);
+            const int lo_last = 4 * (rlast * static_cast<int>(R.ppitch) + L.c);
+            const int rsb = 4 * L.R * static_cast<int>(R.ppitch);
+            const __amdgpu_buffer_rsrc_t bf =
+                __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(R.pf + top), 0, 0x7fffffff, kBufferWord3);
+            const __amdgpu_buffer_rsrc_t bx =
+                __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(R.pfx + top), 0, 0x7fffffff, kBufferWord3);
+            const __amdgpu_buffer_rsrc_t by =
+                __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(R.pfy + top), 0, 0x7fffffff, kBufferWord3);
 #pragma unroll
             for (int j = 0; j < P; ++j) {
-                fb[j] = gx[j] = gy[j] = 0.0f;
-                if (j < L.jmax) {
-                    fb[j] = *af;
-                    gx[j] = *ax;
-                    gy[j] = *ay;
+                if (j < JM - 1) {
+                    fb[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(bf, lo, j * rsb, 0));
+                    gx[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(bx, lo, j * rsb, 0));
+                    gy[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(by, lo, j * rsb, 0));
+                } else if (j == JM - 1) {
+                    fb[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(bf, lo_last, j * rsb, 0));
+                    gx[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(bx, lo_last, j * rsb, 0));
+                    gy[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(by, lo_last, j * rsb, 0));
+                } else {
+                    fb[j] = gx[j] = gy[j] = 0.0f;
                 }
-                af += rs;
-                ax += rs;
-                ay += rs;
             }
         }
         if constexpr (!kQaInLds) __syncthreads();   // cache visible to every wavefront
@@ -953,7 +971,7 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
             const float fm32 = static_cast<float>(cache[0]);
 #pragma unroll
             for (int j = 0; j < P; ++j)
-                if (j < L.jmax) fb[j] -= fm32;
+                if (j < JM) fb[j] -= fm32;
             const double hd = static_cast<double>(h);
             int tox = INT_MIN / 2, toy = INT_MIN / 2;   // staged window origin (global sample coords)
 
@@ -1014,30 +1032,33 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
                     toy = oy;
                     __syncthreads();   // previous window no longer read
                     if (!half) {
-                        // each wavefront fills 64 consecutive window elements per request,
-                        // straight into LDS (no registers, all requests in flight at once)
-                        // the source pointer steps with the element: dr rows and dc
-                        // columns per request, one more row when the column wraps
-                        const float *g = static_cast<const float *>(F.dcoef);
+                        // one buffer request per window row (and 64-column segment),
+                        // straight into LDS: the descriptor holds the window origin, the
+                        // row offset and the LDS destination are uniform and step in
+                        // scalar registers, and a lane's column offset stays fixed, so
+                        // the loop issues no vector instruction (row offsets fit 32 bits:
+                        // the set-up bounds the row pitch)
                         const int lane = t & 63;
-                        const int e_first = (t & ~63);
-                        int e = e_first + lane;
-                        int c = e - (e / ts) * ts;
-                        const int dr = T / ts, dc = T - (T / ts) * ts;
+                        const int nw = T / 64;
+                        const int w0 = __builtin_amdgcn_readfirstlane(wid);
+                        const int oxu = __builtin_amdgcn_readfirstlane(ox);
+                        const int oyu = __builtin_amdgcn_readfirstlane(oy);
                         const int64_t dpitch = F.dpitch;
-                        const float *src = g + static_cast<int64_t>(oy + e / ts) * dpitch + (ox + c);
-                        const int64_t step_a = dr * dpitch + dc, step_b = dpitch - ts;
-                        for (int e0 = e_first; e0 < ts * ts; e0 += T) {
-                            if (e < ts * ts)
-                                __builtin_amdgcn_global_load_lds(
-                                    (const __attribute__((address_space(1))) void *)(src),
-                                    (__attribute__((address_space(3))) void *)(tile + e0), 4, 0, 0);
-                            e += T;
-                            c += dc;
-                            src += step_a;
-                            if (c >= ts) {
-                                c -= ts;
-                                src += step_b;
+                        const float *origin = static_cast<const float *>(F.dcoef) + static_cast<int64_t>(oyu) * dpitch + oxu;
+                        const __amdgpu_buffer_rsrc_t win =
+                            __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(origin), 0, 0x7fffffff, kBufferWord3);
+                        const int rstride = static_cast<int>(4 * nw * dpitch);
+                        for (int c0 = 0; c0 < ts; c0 += 64) {
+                            if (lane < ts - c0) {
+                                const int vo = 4 * (c0 + lane);
+                                int so = static_cast<int>(4 * w0 * dpitch);
+                                float *d = tile + w0 * lp + c0;
+                                for (int r = w0; r < ts; r += nw) {
+                                    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                                        win, (__attribute__((address_space(3))) void *)(d), 4, vo, so, 0, 0);
+                                    so += rstride;
+                                    d += nw * lp;
+                                }
                             }
                         }
                         __builtin_amdgcn_s_waitcnt(0);
@@ -1047,7 +1068,7 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
                         int r = t / ts, c = t - (t / ts) * ts;
                         for (int e = t; e < ts * ts; e += T) {
                             const int64_t go = static_cast<int64_t>(oy + r) * F.dpitch + (ox + c);
-                            tile[e] = to_f32(static_cast<const __half *>(F.dcoef)[go]);
+                            tile[r * lp + c] = to_f32(static_cast<const __half *>(F.dcoef)[go]);
                             r += dr;
                             c += dc;
                             if (c >= ts) {
@@ -1081,11 +1102,8 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
                     // weighted by zero, so every lane runs the same instruction stream
                     const float dyl = static_cast<float>(N - 1 - h);
                     const float Xc = fmaf(A1, dxf, A0), Yc = fmaf(B1, dxf, B0);
-                    const float *tb = tile - ts - 1;
-                    const float tsf = static_cast<float>(ts);
-                    // rows per thread of this subset (a launch may mix subset sizes, P is
-                    // the largest); uniform across the workgroup
-                    const int JM = __builtin_amdgcn_readfirstlane((N + L.R - 1) / L.R);
+                    const float *tb = tile - lp - 1;
+                    const float tsf = static_cast<float>(lp);
                     auto pixel_row = [&](int j) {
                         const bool on = j < L.jmax;
                         const float dy = on ? fmaf(static_cast<float>(j), dyR, dy0) : dyl;
@@ -1103,7 +1121,7 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
                         // tap offset in the window: exact in FP32 (|values| < 2^24), which
                         // avoids a quarter-rate integer multiply per pixel
                         const int off = static_cast<int>(fmaf(fy0, tsf, fx0));
-                        const float g = interp16(tb + off, ts, wx0, wx1, wx2, wx3, wy0, wy1, wy2, wy3);
+                        const float g = interp16(tb + off, lp, wx0, wx1, wx2, wx3, wy0, wy1, wy2, wy3);
                         // a weight rather than a select: the row is then computed on every
                         // lane instead of under a branch, which keeps the rows in one block
                         accumulate<NP>(s, (g - fm32) * (on ? 1.0f : 0.0f), fb[j], gx[j], gy[j], dy);
@@ -1132,7 +1150,7 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
 #pragma unroll
                             for (int r = 0; r < 4; ++r)
 #pragma unroll
-                                for (int c = 0; c < 4; ++c) tap[b][4 * r + c] = q[r * ts + c];
+                                for (int c = 0; c < 4; ++c) tap[b][4 * r + c] = q[r * lp + c];
                         };
                         fetch_row(0, 0);
 #pragma unroll
@@ -1717,9 +1735,9 @@ static void wave_packed_inst(const FrameTable &F, int step, bool f64, int max_ts
 // dispatch
 // ---------------------------------------------------------------------------
 template <int NP, int T, int P>
-static void wave_inst(const FrameTable &F, int step, bool f64, int max_ts, int grid, hipStream_t s)
+static void wave_inst(const FrameTable &F, int step, bool f64, int lds_floats, int grid, hipStream_t s)
 {
-    const size_t lds = static_cast<size_t>(max_ts) * max_ts * sizeof(float);
+    const size_t lds = static_cast<size_t>(lds_floats) * sizeof(float);
     if (f64)
         k_wave<NP, T, P, true><<<grid, T, lds, s>>>(F, step);
     else
@@ -1762,8 +1780,8 @@ int tile_side(int N)
 // same shape and threads per subset, and subset sizes whose rows fit the register
 // block chosen for N (the largest subset of the launch); the LDS window is sized
 // for the largest frame's window side.
-bool launch_wave(const FrameTable &F, int step, int np, int N, int tps, bool f64, int max_ts, int grid,
-                 hipStream_t s)
+bool launch_wave(const FrameTable &F, int step, int np, int N, int tps, bool f64, int max_ts, int lds_floats,
+                 int grid, hipStream_t s)
 {
     const int P = pixels_per_thread(N, tps);
     if (tps < 64) {
@@ -1779,7 +1797,7 @@ bool launch_wave(const FrameTable &F, int step, int np, int N, int tps, bool f64
     }
 #define X(NP_, T_, P_)                                                                                                \
     if (np == NP_ && tps == T_ && P == P_) {                                                                          \
-        wave_inst<NP_, T_, P_>(F, step, f64, max_ts, grid, s);                                      \
+        wave_inst<NP_, T_, P_>(F, step, f64, lds_floats, grid, s);                                  \
         return true;                                                                                                   \
     }
     DIC_TP_CASES(6, X)

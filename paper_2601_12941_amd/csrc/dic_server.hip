@@ -459,17 +459,19 @@ dic_status dic_server_step(dic_server *s, int32_t steps)
             for (size_t i0 = 0; i0 < reqs.size(); i0 += kMaxFrames) {
                 FrameTable table;
                 std::memset(&table, 0, sizeof(table));
-                int nmax = 0, tsmax = 0;
+                int nmax = 0, tsmax = 0, ldsmax = 0;
                 const size_t i1 = std::min(reqs.size(), i0 + kMaxFrames);
                 for (size_t i = i0; i < i1; ++i) {
                     table.f[i - i0] = reqs[i]->F;
-                    nmax = std::max(nmax, reqs[i]->ref->prm.subset_size);
-                    tsmax = std::max(tsmax, reqs[i]->ref->window_side());
+                    const int n = reqs[i]->ref->prm.subset_size, ts = reqs[i]->ref->window_side();
+                    nmax = std::max(nmax, n);
+                    tsmax = std::max(tsmax, ts);
+                    ldsmax = std::max(ldsmax, ts * lds_pitch(n, ts));
                 }
                 table.n = static_cast<int>(i1 - i0);
                 const int np = std::get<0>(g.first), tps = std::get<1>(g.first);
                 const int grid = wave_grid_hint(np, tps, s->device);
-                if (!launch_wave(table, s->step, np, nmax, tps, std::get<2>(g.first) != 0, tsmax, grid, st))
+                if (!launch_wave(table, s->step, np, nmax, tps, std::get<2>(g.first) != 0, tsmax, ldsmax, grid, st))
                     SFAIL(DIC_E_UNSUPPORTED, "no kernel for shape %d, %d threads, subset %d", np, tps, nmax);
             }
         }
