@@ -124,15 +124,18 @@ def accuracy(g, o, w, truth=None):
 
 
 def profiled_traffic():
-    """HBM bytes per batched k_wave launch from the committed FETCH_SIZE / WRITE_SIZE
-    counter runs, if they were taken on the kernel source and compile flags built now."""
+    """HBM bytes per batched k_wave wave step (the launches of both launch chains)
+    from the committed FETCH_SIZE / WRITE_SIZE counter runs, if they were taken on
+    the kernel source and compile flags built now."""
     from paper_2601_12941_amd import build
     rec_path = os.path.join(ROOT, "profiles", "k_wave_2048_batched_traffic.json")
     try:
         rec = json.load(open(rec_path))
     except OSError:
         return None
-    return rec["traffic_bytes_per_launch"] if rec.get("kernel_build_sha256") == build.kernel_build_id() else None
+    if rec.get("kernel_build_sha256") != build.kernel_build_id():
+        return None
+    return rec.get("traffic_bytes_per_wave_step", rec["traffic_bytes_per_launch"])
 
 
 # the launch shapes the autotuner picks on the 2048^2 workload, fixed for the profiled runs
@@ -147,8 +150,46 @@ def _short(name):
     return name.split("(")[0]
 
 
-def summarize_trace(d, out):
-    """profiles/*.md from a rocprofv3 --kernel-trace --stats directory."""
+BATCHED_KERNEL = "k_wave<6, 64, 16, true>"
+
+
+def batched_steps(trace_dir, kb=BATCHED_KERNEL):
+    """The batched k_wave launches of a rocprofv3 kernel trace: launch chains (the
+    streams they ran on), launches, their average duration, and the duration of a
+    wave step (the union of the time the chains' launches of one wave index run,
+    which overlap), averaged over the steps."""
+    import csv
+    f = next(os.path.join(r, x) for r, _, fs in os.walk(trace_dir) for x in fs if x.endswith("kernel_trace.csv"))
+    iv = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Stream_Id"])
+          for r in csv.DictReader(open(f)) if _short(r["Kernel_Name"]) == kb]
+    chains = len({q for _, _, q in iv})
+    iv.sort()
+    union, cs, ce = 0, iv[0][0], iv[0][1]
+    for a, b, _ in iv[1:]:
+        if a > ce:
+            union += ce - cs
+            cs, ce = a, b
+        else:
+            ce = max(ce, b)
+    union += ce - cs
+    steps = len(iv) / chains
+    return dict(chains=chains, launches=len(iv), avg_launch_us=sum(b - a for a, b, _ in iv) / len(iv) / 1e3,
+                step_us=union / steps / 1e3, steps=steps)
+
+
+def _live_step_us(log):
+    """roofline.avg_launch_us of the bench JSON line in a run's output, if any."""
+    if not log or not os.path.exists(log):
+        return None
+    for ln in reversed(open(log, errors="replace").read().splitlines()):
+        if ln.startswith("{") and '"roofline"' in ln:
+            return json.loads(ln)["roofline"]["avg_launch_us"]
+    return None
+
+
+def summarize_trace(d, out, log=None):
+    """profiles/*.md from a rocprofv3 --kernel-trace --stats directory (and the
+    profiled run's output, for the live wave-step figure it printed)."""
     import csv
     stats = next(os.path.join(r, f) for r, _, fs in os.walk(d) for f in fs if f.endswith("kernel_stats.csv"))
     rows = list(csv.DictReader(open(stats)))
@@ -159,7 +200,8 @@ def summarize_trace(d, out):
              "```", "rocprofv3 --kernel-trace --stats -f csv -d <out> -o run -- python3 " + PROFILE_BENCH, "```", "",
              "Summary written by `python bench.py --summarize-trace <out> --summary-out <this file>`.", "",
              "Workload: 2048x2048 u16 speckle, sinusoidal u, subset 31, step 2, affine (1 010 025 active subsets per "
-             "frame, 1005 waves). Batched form: 32 frames per launch, %d threads per subset, %d-sample window "
+             "frame, 1005 waves). Batched form: 32 frames per call in two launch chains of 16 frames on two "
+             "streams, %d threads per subset, %d-sample window "
              "(the autotuner's pick on this workload); plain form: one frame per call, %d threads per subset, "
              "%d-sample window (64 and 128 threads tie within 1%% for the plain form)." % (
                  PROFILE_SHAPES["tps"], PROFILE_SHAPES["tile"], PROFILE_SHAPES["plain_tps"],
@@ -169,9 +211,14 @@ def summarize_trace(d, out):
         lines.append("| `%s` | %s | %.1f | %.1f | %.2f | %.1f | %.1f |" % (
             _short(r["Name"]), r["Calls"], float(r["TotalDurationNs"]) / 1e6, float(r["AverageNs"]) / 1e3,
             float(r["Percentage"]), float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3))
-    lines += ["", "The batched-form k_wave average above is the launch duration `bench.py` measures live with HIP events "
-              "(`roofline.avg_launch_us`; the live figure spans back-to-back launches, so it includes the few-microsecond "
-              "gaps between them).",
+    b = batched_steps(d)
+    live = _live_step_us(log)
+    lines += ["", "Batched form (`%s`): %d launches on %d streams, %.1f us each on average; the two chains' launches "
+              "of one wave index run side by side, so a wave step (the union of the time they run) takes %.1f us "
+              "over %d wave steps. `bench.py` measures the wave step live with HIP events (`roofline.avg_launch_us`, "
+              "chunks of back-to-back steps including the few-microsecond gaps between them)%s." % (
+                  BATCHED_KERNEL, b["launches"], b["chains"], b["avg_launch_us"], b["step_us"], b["steps"],
+                  ": %.1f us in this profiled run" % live if live else ""),
               "Kernel build at the time of this profile: sha256 `%s` of `paper_2601_12941_amd/csrc/dic_kernels.hip` "
               "and its compile flags (`build.kernel_build_id()`)."
               % kid]
@@ -245,14 +292,21 @@ def summarize_pmc(fetch_dir, write_dir, cfetch_dir, cwrite_dir, out_md, out_json
         w = wr.get(k, (0.0, 0))[0]
         lines.append("| `%s` | %d | %.1f | %.2f | %.1f | %.2f |" % (k, fe[k][1], fe[k][0], fe[k][0] * 1024 * ff / 1e6,
                                                                     w, w * 1024 * wf / 1e6))
-    kb = "k_wave<6, 64, 16, true>"
+    kb = BATCHED_KERNEL
     fetch_b = fe[kb][0] * 1024 * ff
     write_b = wr[kb][0] * 1024 * wf
-    lines += ["", "Kernel build at the time of these counters: sha256 `%s` of the source and its compile flags." % kid]
+    # one batched step = 1020 wave steps of 2 launch chains on this workload
+    chains = max(1, round(fe[kb][1] / 1020.0))
+    lines += ["", "The batched form runs two launch chains of 16 frames: %d dispatches of `%s` per step, so a wave "
+              "step (one launch of each chain) moves %.1f MB fetched + %.1f MB written." % (
+                  fe[kb][1], kb, chains * fetch_b / 1e6, chains * write_b / 1e6),
+              "Kernel build at the time of these counters: sha256 `%s` of the source and its compile flags." % kid]
     open(out_md, "w").write("\n".join(lines) + "\n")
-    json.dump({"kernel": kb + " (batched form, 32 frames per launch)", "kernel_build_sha256": kid,
+    json.dump({"kernel": kb + " (batched form, 32 frames per call in %d launch chains)" % chains,
+               "kernel_build_sha256": kid, "launch_chains": chains,
                "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
-               "traffic_bytes_per_launch": fetch_b + write_b, "dispatches": fe[kb][1],
+               "traffic_bytes_per_launch": fetch_b + write_b,
+               "traffic_bytes_per_wave_step": chains * (fetch_b + write_b), "dispatches": fe[kb][1],
                "copy_calibration": {"bytes": copy_bytes, "fetch_kib": cf, "write_kib": cw, "fetch_factor": ff,
                                     "write_factor": wf}}, open(out_json, "w"), indent=1)
     print("wrote", out_md, out_json)
@@ -275,11 +329,11 @@ def summarize_l2(bench_dir, copy_dir, trace_dir, out_md):
     b, c = per_kernel(bench_dir), per_kernel(copy_dir)
     copy_reads = max(v[0] for k, v in c.items() if k[1] == "TCC_READ_sum")
     req_b = 256 * (1 << 20) / copy_reads
-    kb = "k_wave<6, 64, 16, true>"
+    kb = BATCHED_KERNEL
     rd, n = b[(kb, "TCC_READ_sum")]
     hit, miss = b[(kb, "TCC_HIT_sum")][0], b[(kb, "TCC_MISS_sum")][0]
-    stats = next(os.path.join(r, f) for r, _, fs in os.walk(trace_dir) for f in fs if f.endswith("kernel_stats.csv"))
-    avg_us = next(float(r["AverageNs"]) / 1e3 for r in csv.DictReader(open(stats)) if _short(r["Name"]) == kb)
+    bt = batched_steps(trace_dir)
+    avg_us, chains = bt["step_us"], bt["chains"]
     from paper_2601_12941_amd import build
     lines = ["# k_wave on the 2048^2 workload: L2 (TCC) counters", "",
              "Commands (each a separate pass; rocprofv3 run from /tmp with TMPDIR=/tmp, from the repository root "
@@ -293,11 +347,13 @@ def summarize_l2(bench_dir, copy_dir, trace_dir, out_md):
              "request (one 128 B line)." % (copy_reads, req_b), "",
              "| Kernel | Dispatches | TCC_READ_sum / dispatch | L2 read bytes / dispatch | TCC_HIT_sum | TCC_MISS_sum "
              "| hit rate |", "|---|---|---|---|---|---|---|",
-             "| `%s` (batched, 32 frames) | %d | %.0f | %.0f MB | %.0f | %.0f | %.1f %% |" % (
+             "| `%s` (batched, one launch chain of 16 frames) | %d | %.0f | %.0f MB | %.0f | %.0f | %.1f %% |" % (
                  kb, n, rd, rd * 128 / 1e6, hit, miss, 100.0 * hit / max(1.0, hit + miss)), "",
-             "Over the batched launch's %.1f us (kernel trace of the same build) that is %.1f TB/s of L2 reads; the "
+             "A wave step (one launch of each of the %d chains) reads %.0f MB from L2; over the %.1f us of a wave "
+             "step (kernel trace of the same build) that is %.1f TB/s of L2 reads; the "
              "achievable L2 re-read rate measured by `dic_roof_cache_read` is 32.6 TB/s "
-             "(`achievable_rates_mi355x.md`)." % (avg_us, rd * 128 / (avg_us * 1e-6) / 1e12), "",
+             "(`achievable_rates_mi355x.md`)." % (chains, chains * rd * 128 / 1e6, avg_us,
+                                                   chains * rd * 128 / (avg_us * 1e-6) / 1e12), "",
              "Kernel build at the time of these counters: sha256 `%s`." % build.kernel_build_id()]
     open(out_md, "w").write("\n".join(lines) + "\n")
     print("wrote", out_md)
@@ -317,15 +373,16 @@ def summarize_sq(sq_dir, trace_dir, out_md):
         k = (_short(r["Kernel_Name"]), r["Counter_Name"])
         acc[k] = acc.get(k, 0.0) + float(r["Counter_Value"])
         disp.setdefault(k, set()).add(r["Dispatch_Id"])
-    kb = "k_wave<6, 64, 16, true>"
+    kb = BATCHED_KERNEL
     v = {c: acc[(kb, c)] / len(disp[(kb, c)]) for c in SQ_COUNTERS if (kb, c) in acc}
     n = len(disp[(kb, "SQ_WAVES")])
-    stats = next(os.path.join(r, x) for r, _, fs in os.walk(trace_dir) for x in fs if x.endswith("kernel_stats.csv"))
-    avg_us = next(float(r["AverageNs"]) / 1e3 for r in csv.DictReader(open(stats)) if _short(r["Name"]) == kb)
+    bt = batched_steps(trace_dir)
+    avg_us, chains = bt["step_us"], bt["chains"]
     # workgroups that find no subset exit at once: the subsets of a launch are the
-    # converged subsets the benchmark counts (31 687 per launch on this workload)
-    subsets = 1010025 * 32 / 1020.0
-    issue = v["SQ_INSTS_VALU"] / (avg_us * 1e-6)
+    # converged subsets the benchmark counts (1 010 025 per frame, 32 frames in
+    # `chains` launch chains, 1020 wave steps)
+    subsets = 1010025 * 32 / 1020.0 / chains
+    issue = chains * v["SQ_INSTS_VALU"] / (avg_us * 1e-6)
     simd_rate = 256 * 4 * 2.4e9 / 4          # one wave64 VALU instruction per SIMD every 4 clocks
     from paper_2601_12941_amd import build
     lines = ["# k_wave on the 2048^2 workload: SQ instruction counters", "",
@@ -339,10 +396,12 @@ def summarize_sq(sq_dir, trace_dir, out_md):
         if c in v:   # wavefronts and busy cycles are per launch, not per subset
             per = "" if c in ("SQ_WAVES", "SQ_BUSY_CYCLES") else "%.1f" % (v[c] / subsets)
             lines.append("| `%s` | %.0f | %s |" % (c, v[c], per))
-    lines += ["", "Subsets per launch: %.1f (1 010 025 per frame, 32 frames, 1020 launches per step)." % subsets,
-              "VALU issue over the %.1f us launch (kernel trace of the same build): %.2e instructions/s, %.0f %% of "
-              "the %.2e that 1024 SIMDs issue at one wave64 instruction every 4 clocks (2.4 GHz)." % (
-                  avg_us, issue, 100.0 * issue / simd_rate, simd_rate), "",
+    lines += ["", "Subsets per launch: %.1f (1 010 025 per frame, 32 frames in %d launch chains, 1020 wave steps)."
+              % (subsets, chains),
+              "VALU issue over the %.1f us wave step (the union of the %d chains' concurrent launches, kernel trace of "
+              "the same build): %.2e instructions/s, %.0f %% of the %.2e that 1024 SIMDs issue at one wave64 "
+              "instruction every 4 clocks (2.4 GHz)." % (avg_us, chains, issue, 100.0 * issue / simd_rate, simd_rate),
+              "",
               "Kernel build at the time of these counters: sha256 `%s`." % build.kernel_build_id()]
     open(out_md, "w").write("\n".join(lines) + "\n")
     print("wrote", out_md)
@@ -980,6 +1039,7 @@ def main():
     ap.add_argument("--parity-samples", type=int, default=8, help="serve: requests checked against the oracle")
     ap.add_argument("--summarize-trace", metavar="DIR", help="write the kernel-trace summary of a rocprofv3 run")
     ap.add_argument("--summary-out", default=os.path.join(ROOT, "profiles", "k_wave_2048_kernel_trace.md"))
+    ap.add_argument("--trace-log", metavar="LOG", help="--summarize-trace: the profiled run's output (its JSON line)")
     ap.add_argument("--summarize-sq", nargs=2, metavar=("SQ", "TRACE"),
                     help="write the SQ instruction-counter summary from a rocprofv3 --pmc run and a kernel trace")
     ap.add_argument("--summarize-l2", nargs=3, metavar=("BENCH", "COPY", "TRACE"),
@@ -993,7 +1053,7 @@ def main():
                     help="only run a plain 256 MiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.summarize_trace:
-        summarize_trace(args.summarize_trace, args.summary_out)
+        summarize_trace(args.summarize_trace, args.summary_out, args.trace_log)
         return
     if args.summarize_sq:
         summarize_sq(*args.summarize_sq, os.path.join(ROOT, "profiles", "k_wave_2048_sq_counters.md"))
@@ -1167,7 +1227,10 @@ def main():
                 "traffic": traffic,
                 "flop_per_px_iter": FLOP_PER_PX_IT[w.shape], "avg_launch_us": avg_launch_ms * 1e3,
                 "launches_per_step": launches / args.steps,
-                "subsets_per_launch": conv / max(1, launches)}
+                "subsets_per_launch": conv / max(1, launches),
+                "launch_chains": last["launch_chains"],
+                "launch": "one wave step: the launches of every launch chain for one wave index, which run side "
+                          "by side on their streams; avg_launch_us is the duration of a wave step"}
     # achievable denominators measured on this GPU beside the published peaks: FP32 FMA
     # issue as the library is built (no packed FP32) and HBM streaming reads
     if not args.no_probes:

@@ -147,7 +147,11 @@ typedef struct {
     double ms_icgn;         /* device time from the first to the last IC-GN wave kernel */
     double ms_prefilter;    /* device time of the deformed-image prefilter */
     double ms_wave_kernels; /* device time of the chunks of back-to-back wave launches, host gaps excluded */
-    int32_t wave_launches;  /* IC-GN wave kernel launches of the last call */
+    int32_t wave_launches;  /* IC-GN wave steps of the last call: one wave kernel launch per step and
+                               launch chain */
+    int32_t launch_chains;  /* streams the wave launches of the last call ran on: a batched call of
+                               16 or 32 frames runs its two halves as two chains, each frame's waves
+                               in order on its chain's stream; otherwise 1 */
 } dic_stats;
 
 /* Create a context on HIP device `device`, ordering its work on `hip_stream`

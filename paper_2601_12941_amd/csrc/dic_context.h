@@ -91,7 +91,9 @@ struct dic_ctx {
     int32_t *d_centre = nullptr;
     double *d_zbuf = nullptr;
     int zbuf_capacity = 0, centre_capacity = 0;
-    int32_t *d_wave_total = nullptr;
+    int32_t *d_wave_total = nullptr;   // wave sizes, [kMaxChains][nodes + 130]: one row per launch chain
+    hipStream_t chain_stream[kMaxChains] = {};   // launch chains 1.. of batched calls (default priority)
+    hipEvent_t chain_ev[kMaxChains] = {};        // fork (0) and join (1..) events of the chains
     RefView *d_view = nullptr;   // device copy of view(), read by the wave kernel
     int32_t *h_pinned = nullptr;
     unsigned long long *h_stats = nullptr;  // pinned: 4 counters per frame, then the last frame's seed shift

@@ -74,6 +74,13 @@ dic_status dic_destroy(dic_ctx *c)
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto &e : c->chunk_ev) (void)hipEventDestroy(e);
+    for (auto &e : c->chain_ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto &q : c->chain_stream)
+        if (q) {
+            (void)hipStreamSynchronize(q);
+            (void)hipStreamDestroy(q);
+        }
     delete c;
     return DIC_OK;
 }
@@ -197,7 +204,7 @@ dic_status dic_set_reference(dic_ctx *c, const dic_image *ref, const uint8_t *ro
     HIPCHK(hipMalloc(&c->flag, c->nodes));
     const size_t rowb = c->W * pixel_size(ref->pixel);
     HIPCHK(hipMalloc(&c->ref_raw, rowb * c->H));
-    HIPCHK(hipMalloc(&c->d_wave_total, sizeof(int32_t) * (c->nodes + 130)));
+    HIPCHK(hipMalloc(&c->d_wave_total, sizeof(int32_t) * kMaxChains * (c->nodes + 130)));
     HIPCHK(hipMemcpy2DAsync(c->ref_raw, rowb, ref->data, ref->pitch_bytes, rowb, c->H, hipMemcpyDeviceToDevice, s));
     if (!variant) HIPCHK(hipMemsetAsync(c->cache, 0, sizeof(double) * cache_slots(c->np) * c->nodes, s));
 
@@ -325,19 +332,49 @@ dic_status run_frames(dic_ctx *c, const dic_image *defs, int nframes, int nseeds
     HIPCHK(hipEventRecord(c->ev[1], s));
     HIPCHK(hipMemcpyAsync(d_centre, h_centre, sizeof(int32_t) * 2 * nframes * nseeds, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(d_frames, hf, sizeof(FrameState) * nframes, hipMemcpyHostToDevice, s));
-    launch_zero32(c->d_wave_total, c->nodes + 130, s);
+    launch_zero32(c->d_wave_total, kMaxChains * (c->nodes + 130), s);
     launch_seed_search(R, d_frames, nframes, nseeds, c->prm.seed_radius, d_centre, d_zbuf, s);
     launch_seed_pick(R, d_frames, nframes, nseeds, c->prm.seed_radius, d_centre, d_zbuf, s);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(c->ev[2], s));
 
     const int grid = c->variant ? wave_grid_hint(c->np, 256, c->device) : wave_grid_hint(c->np, c->tps, c->device);
-    FrameTable table;
-    std::memset(&table, 0, sizeof(table));
-    for (int f = 0; f < nframes; ++f) table.f[f] = hf[f];
-    table.n = nframes;
+    // Launch chains: the frames are independent, so a batch is split into groups
+    // whose waves run on streams of their own.  Wave k + 1 of a group waits only
+    // for wave k of that group, and the last workgroups of one group's launch share
+    // the GPU with the other groups' launches instead of leaving it idle.
+    const int nchain = launch_chains(nframes);
+    const int per = nframes / nchain;
+    for (int g = 1; g < nchain; ++g)
+        if (!c->chain_stream[g]) HIPCHK(hipStreamCreateWithFlags(&c->chain_stream[g], hipStreamNonBlocking));
+    for (int g = 0; g < nchain && nchain > 1; ++g)
+        if (!c->chain_ev[g]) HIPCHK(hipEventCreateWithFlags(&c->chain_ev[g], hipEventDisableTiming));
+    hipStream_t cs[kMaxChains];
+    for (int g = 0; g < kMaxChains; ++g) cs[g] = g == 0 ? s : c->chain_stream[g];
+    FrameTable table[kMaxChains];
+    std::memset(table, 0, sizeof(table));
+    for (int g = 0; g < nchain; ++g) {
+        for (int f = 0; f < per; ++f) table[g].f[f] = hf[g * per + f];
+        table[g].n = per;
+    }
+    if (nchain > 1) {
+        // the other chains start after the frames' set-up and seeds on the first stream
+        HIPCHK(hipEventRecord(c->chain_ev[0], s));
+        for (int g = 1; g < nchain; ++g) HIPCHK(hipStreamWaitEvent(cs[g], c->chain_ev[0], 0));
+    }
+    const int64_t tstride = c->nodes + 130;   // wave sizes of chain g at d_wave_total + g * tstride
     const bool f64 = c->prm.reduce_fp64 != 0;
     int k = 0, chunk = 4, nchunk = 0;
+    bool live[kMaxChains];
+    for (int g = 0; g < kMaxChains; ++g) live[g] = g < nchain;
+    auto join = [&]() -> dic_status {
+        // the first stream waits for the other chains' work so far
+        for (int g = 1; g < nchain; ++g) {
+            HIPCHK(hipEventRecord(c->chain_ev[g], cs[g]));
+            HIPCHK(hipStreamWaitEvent(s, c->chain_ev[g], 0));
+        }
+        return DIC_OK;
+    };
     for (;;) {
         if (chunk_timing) {
             if (static_cast<int>(c->chunk_ev.size()) < 2 * (nchunk + 1)) {
@@ -349,20 +386,46 @@ dic_status run_frames(dic_ctx *c, const dic_image *defs, int nframes, int nseeds
             }
             HIPCHK(hipEventRecord(c->chunk_ev[2 * nchunk], s));
         }
-        for (int j = 0; j < chunk && k <= c->nodes; ++j, ++k)
-            if (c->variant ? !launch_wave_var(table, k, c->np, grid, s)
-                           : !launch_wave(table, k, c->np, c->prm.subset_size, c->tps, f64, R.ts, R.ts * R.lp, grid, s))
-                FAIL(DIC_E_UNSUPPORTED, "no kernel for shape %d, %d threads, subset %d", c->np, c->tps,
-                     c->prm.subset_size);
+        int kend = k;
+        for (int g = 0; g < nchain; ++g) {
+            if (!live[g]) continue;
+            int kk = k;
+            for (int j = 0; j < chunk && kk <= c->nodes; ++j, ++kk)
+                if (c->variant ? !launch_wave_var(table[g], kk, c->np, grid, cs[g])
+                               : !launch_wave(table[g], kk, c->np, c->prm.subset_size, c->tps, f64, R.ts,
+                                              R.ts * R.lp, grid, cs[g]))
+                    FAIL(DIC_E_UNSUPPORTED, "no kernel for shape %d, %d threads, subset %d", c->np, c->tps,
+                         c->prm.subset_size);
+            kend = kk;
+        }
+        k = kend;
         HIPCHK(hipGetLastError());
-        if (chunk_timing) HIPCHK(hipEventRecord(c->chunk_ev[2 * nchunk + 1], s));
+        // size of the next wave of each chain, summed over its frames
+        for (int g = 0; g < nchain; ++g) {
+            if (!live[g]) continue;
+            launch_count_wave(d_frames + g * per, per, k, c->d_wave_total + g * tstride, cs[g]);
+            HIPCHK(hipMemcpyAsync(c->h_pinned + g, c->d_wave_total + g * tstride + k, sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, cs[g]));
+        }
+        if (chunk_timing) {
+            const dic_status js = join();
+            if (js != DIC_OK) return js;
+            HIPCHK(hipEventRecord(c->chunk_ev[2 * nchunk + 1], s));
+        }
         ++nchunk;
-        // size of the next wave, summed over the frames
-        launch_count_wave(d_frames, nframes, k, c->d_wave_total, s);
-        HIPCHK(hipMemcpyAsync(c->h_pinned, c->d_wave_total + k, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        if (c->h_pinned[0] == 0 || k > c->nodes) break;
+        for (int g = 0; g < nchain; ++g)
+            if (live[g]) HIPCHK(hipStreamSynchronize(cs[g]));
+        bool any = false;
+        for (int g = 0; g < nchain; ++g) {
+            if (live[g]) live[g] = c->h_pinned[g] != 0 && k <= c->nodes;
+            any = any || live[g];
+        }
+        if (!any) break;
         chunk = std::min(chunk * 2, 64);
+    }
+    {
+        const dic_status js = join();
+        if (js != DIC_OK) return js;
     }
     HIPCHK(hipEventRecord(c->ev[3], s));
     for (int f = 0; f < nframes; ++f) {
@@ -400,6 +463,7 @@ dic_status run_frames(dic_ctx *c, const dic_image *defs, int nframes, int nseeds
     HIPCHK(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
     S.ms_prefilter = ms;
     S.wave_launches = k;
+    S.launch_chains = nchain;
     if (chunk_timing) {
         for (int q = 0; q < nchunk; ++q) {
             HIPCHK(hipEventElapsedTime(&ms, c->chunk_ev[2 * q], c->chunk_ev[2 * q + 1]));

@@ -512,6 +512,7 @@ dic_status dic_server_step(dic_server *s, int32_t steps)
                 S.frames = 1;
                 S.threads_per_subset = r->ref->tps;
                 S.waves = static_cast<int32_t>(stat[4 * i + 3]);
+                S.launch_chains = 1;
                 release(s, r);
                 r->state = 2;
                 ++s->completed;

@@ -65,7 +65,7 @@ class DicStats(C.Structure):
                 ("iterations", C.c_int64), ("waves", C.c_int32), ("frames", C.c_int32),
                 ("threads_per_subset", C.c_int32), ("seed_du", C.c_int32), ("seed_dv", C.c_int32),
                 ("ms_total", C.c_double), ("ms_icgn", C.c_double), ("ms_prefilter", C.c_double),
-                ("ms_wave_kernels", C.c_double), ("wave_launches", C.c_int32)]
+                ("ms_wave_kernels", C.c_double), ("wave_launches", C.c_int32), ("launch_chains", C.c_int32)]
 
 
 class DicMwParams(C.Structure):

@@ -62,7 +62,7 @@ int main(void) {
   printf("dic_result %zu\n", sizeof(dic_result));
   F(dic_result, p) F(dic_result, zncc) F(dic_result, iters) F(dic_result, status) F(dic_result, wave)
   printf("dic_stats %zu\n", sizeof(dic_stats));
-  F(dic_stats, waves) F(dic_stats, ms_total) F(dic_stats, ms_wave_kernels) F(dic_stats, wave_launches)
+  F(dic_stats, waves) F(dic_stats, ms_total) F(dic_stats, ms_wave_kernels) F(dic_stats, wave_launches) F(dic_stats, launch_chains)
   printf("dic_server_params %zu\n", sizeof(dic_server_params));
   F(dic_server_params, max_active) F(dic_server_params, hbm_budget_bytes)
   printf("dic_server_stats %zu\n", sizeof(dic_server_stats));

@@ -75,10 +75,16 @@ def test_batch_equals_plain(nframes):
     eng.set_reference(dic.to_device_image(ref), torch.from_numpy(roi).cuda(), **w.params())
     plain = [eng.correlate(dic.to_device_image(f), w.seeds) for f in frames]
     batch = eng.correlate_batch([dic.to_device_image(f) for f in frames], w.seeds)
+    st = eng.stats()
+    # 16 and 32 frames run as two launch chains of half the frames on two streams;
+    # a second call reuses the frame buffers the first call's chains wrote
+    assert st["frames"] == nframes and st["launch_chains"] == (2 if nframes % 16 == 0 else 1)
+    again = eng.correlate_batch([dic.to_device_image(f) for f in frames], w.seeds)
     torch.cuda.synchronize()
-    for a, b in zip(plain, batch):
+    for a, b, c in zip(plain, batch, again):
         for k in a:
             assert torch.equal(a[k], b[k]), k
+            assert torch.equal(a[k], c[k]), k
 
 
 def test_batch_frame_limit():
