@@ -332,7 +332,7 @@ dic_status run_frames(dic_ctx *c, const dic_image *defs, int nframes, int nseeds
     HIPCHK(hipEventRecord(c->ev[1], s));
     HIPCHK(hipMemcpyAsync(d_centre, h_centre, sizeof(int32_t) * 2 * nframes * nseeds, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(d_frames, hf, sizeof(FrameState) * nframes, hipMemcpyHostToDevice, s));
-    launch_zero32(c->d_wave_total, kMaxChains * (c->nodes + 130), s);
+    launch_zero32(c->d_wave_total, launch_chains(nframes) * (c->nodes + 130), s);
     launch_seed_search(R, d_frames, nframes, nseeds, c->prm.seed_radius, d_centre, d_zbuf, s);
     launch_seed_pick(R, d_frames, nframes, nseeds, c->prm.seed_radius, d_centre, d_zbuf, s);
     HIPCHK(hipGetLastError());
@@ -387,16 +387,23 @@ dic_status run_frames(dic_ctx *c, const dic_image *defs, int nframes, int nseeds
             HIPCHK(hipEventRecord(c->chunk_ev[2 * nchunk], s));
         }
         int kend = k;
-        for (int g = 0; g < nchain; ++g) {
+        bool launched = true;
+        for (int g = 0; g < nchain && launched; ++g) {
             if (!live[g]) continue;
             int kk = k;
-            for (int j = 0; j < chunk && kk <= c->nodes; ++j, ++kk)
-                if (c->variant ? !launch_wave_var(table[g], kk, c->np, grid, cs[g])
-                               : !launch_wave(table[g], kk, c->np, c->prm.subset_size, c->tps, f64, R.ts,
-                                              R.ts * R.lp, grid, cs[g]))
-                    FAIL(DIC_E_UNSUPPORTED, "no kernel for shape %d, %d threads, subset %d", c->np, c->tps,
-                         c->prm.subset_size);
+            for (int j = 0; j < chunk && kk <= c->nodes && launched; ++j, ++kk)
+                launched = c->variant ? launch_wave_var(table[g], kk, c->np, grid, cs[g])
+                                      : launch_wave(table[g], kk, c->np, c->prm.subset_size, c->tps, f64, R.ts,
+                                                    R.ts * R.lp, grid, cs[g]);
             kend = kk;
+        }
+        if (!launched) {
+            // no kernel for these parameters: let the chains' work so far finish on
+            // the call's stream before reporting it
+            const dic_status js = join();
+            if (js != DIC_OK) return js;
+            FAIL(DIC_E_UNSUPPORTED, "no kernel for shape %d, %d threads, subset %d", c->np, c->tps,
+                 c->prm.subset_size);
         }
         k = kend;
         HIPCHK(hipGetLastError());

@@ -98,6 +98,8 @@ struct dic_server {
     int32_t *d_next = nullptr;
     int32_t *h_next = nullptr;        // pinned
     FrameState *h_frames = nullptr;   // pinned
+    hipStream_t stream2 = nullptr;    // second launch chain (default priority)
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 #define SFAIL(code, ...)                                                                                              \
@@ -448,13 +450,33 @@ dic_status dic_server_step(dic_server *s, int32_t steps)
     }
 
     // ---- launch steps: one launch per (shape, threads per subset, precision) group
-    std::map<std::tuple<int, int, int>, std::vector<Request *>> groups;
+    // and launch chain.  The requests are independent, so with two or more active
+    // ones every group is split into two chains on two streams (alternate requests):
+    // a request's waves stay in order on its chain's stream, and one chain's launch
+    // fills the GPU while the other's last workgroups finish.
+    std::map<std::tuple<int, int, int>, std::vector<Request *>> groups[2];
+    const int nchain = s->active.size() >= 2 ? 2 : 1;
+    if (nchain == 2 && !s->stream2) {
+        SHIP(hipStreamCreateWithFlags(&s->stream2, hipStreamNonBlocking));
+        SHIP(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
+        SHIP(hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming));
+    }
+    const hipStream_t chain_stream[2] = {st, nchain == 2 ? s->stream2 : st};
+    std::map<std::tuple<int, int, int>, int> seen;
     for (Request *r : s->active) {
         const dic_ctx *c = r->ref;
-        groups[std::make_tuple(c->np, c->tps, c->prm.reduce_fp64)].push_back(r);
+        const auto key = std::make_tuple(c->np, c->tps, c->prm.reduce_fp64);
+        const int nth = seen[key]++;
+        groups[nchain == 2 ? nth % 2 : 0][key].push_back(r);
+    }
+    if (nchain == 2) {
+        // the second chain starts after this call's admissions on the serving stream
+        SHIP(hipEventRecord(s->ev_fork, st));
+        SHIP(hipStreamWaitEvent(s->stream2, s->ev_fork, 0));
     }
     for (int q = 0; q < steps; ++q) {
-        for (auto &g : groups) {
+        for (int ch = 0; ch < nchain; ++ch)
+        for (auto &g : groups[ch]) {
             const auto &reqs = g.second;
             for (size_t i0 = 0; i0 < reqs.size(); i0 += kMaxFrames) {
                 FrameTable table;
@@ -471,11 +493,22 @@ dic_status dic_server_step(dic_server *s, int32_t steps)
                 table.n = static_cast<int>(i1 - i0);
                 const int np = std::get<0>(g.first), tps = std::get<1>(g.first);
                 const int grid = wave_grid_hint(np, tps, s->device);
-                if (!launch_wave(table, s->step, np, nmax, tps, std::get<2>(g.first) != 0, tsmax, ldsmax, grid, st))
+                if (!launch_wave(table, s->step, np, nmax, tps, std::get<2>(g.first) != 0, tsmax, ldsmax, grid,
+                                 chain_stream[ch])) {
+                    if (nchain == 2) {
+                        SHIP(hipEventRecord(s->ev_join, s->stream2));
+                        SHIP(hipStreamWaitEvent(st, s->ev_join, 0));
+                    }
                     SFAIL(DIC_E_UNSUPPORTED, "no kernel for shape %d, %d threads, subset %d", np, tps, nmax);
+                }
             }
         }
         ++s->step;
+    }
+    if (nchain == 2) {
+        // the serving stream continues after both chains
+        SHIP(hipEventRecord(s->ev_join, s->stream2));
+        SHIP(hipStreamWaitEvent(st, s->ev_join, 0));
     }
     SHIP(hipGetLastError());
 
@@ -579,6 +612,12 @@ dic_status dic_server_destroy(dic_server *s)
     dfree(s->d_next);
     if (s->h_next) (void)hipHostFree(s->h_next);
     if (s->h_frames) (void)hipHostFree(s->h_frames);
+    if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+    if (s->ev_join) (void)hipEventDestroy(s->ev_join);
+    if (s->stream2) {
+        (void)hipStreamSynchronize(s->stream2);
+        (void)hipStreamDestroy(s->stream2);
+    }
     delete s;
     return DIC_OK;
 }
