@@ -150,8 +150,8 @@ typedef struct {
     int32_t wave_launches;  /* IC-GN wave steps of the last call: one wave kernel launch per step and
                                launch chain */
     int32_t launch_chains;  /* streams the wave launches of the last call ran on: a batched call of
-                               16 or 32 frames runs its two halves as two chains, each frame's waves
-                               in order on its chain's stream; otherwise 1 */
+                               16, 32, 48 or 64 frames, or of more than 32, runs its two halves as two
+                               chains, each frame's waves in order on its chain's stream; otherwise 1 */
 } dic_stats;
 
 /* Create a context on HIP device `device`, ordering its work on `hip_stream`
@@ -206,9 +206,11 @@ dic_status dic_correlate(dic_ctx *c, const dic_image *def, const dic_seed *seeds
 
 /*
  * Correlate `nframes` deformed images against the same reference in one
- * batched pass: every frontier wave of every frame goes into one launch.
+ * batched pass: wave k of every frame goes into one launch, or, for 16, 32, 48
+ * or 64 frames and for more than 32, into one launch per launch chain (the two
+ * halves of the frames on two streams; see dic_stats.launch_chains).
  * seeds: nframes * nseeds host seeds (frame-major); outs: nframes results.
- * 1 <= nframes <= 32 (DIC_E_INVAL otherwise).  Each frame's results equal
+ * 1 <= nframes <= 64 (DIC_E_INVAL otherwise).  Each frame's results equal
  * those of dic_correlate on that frame alone.
  */
 dic_status dic_correlate_batch(dic_ctx *c, const dic_image *defs, int32_t nframes, const dic_seed *seeds,

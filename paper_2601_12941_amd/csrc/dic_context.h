@@ -14,6 +14,15 @@
 
 namespace dicmi {
 
+// Launch chains of a batched call: groups of frames whose waves run on streams of
+// their own (the frames are independent; only a frame's own waves are ordered).
+// Two halves when the frame count splits into two groups of a multiple of 8 (each
+// group keeps the frame-to-XCD affinity of the wave kernel) or when one launch
+// cannot carry all frames; chain g holds frames [g n / chains, (g + 1) n / chains).
+constexpr int kMaxChains = 4;
+constexpr int kMaxBatch = 2 * kMaxFrames;   // frames one batched call may carry
+inline int launch_chains(int nframes) { return (nframes % 16 == 0 || nframes > kMaxFrames) ? 2 : 1; }
+
 struct FrameBuf {
     void *dcoef_base = nullptr;  // padded deformed coefficients
     uint64_t *pkey = nullptr;
@@ -230,7 +239,7 @@ inline dic_status ensure_frames(dic_ctx *c, int n)
         c->frames.push_back(f);
     }
     (void)np;
-    if (!c->d_frames) HIPCHK(hipMalloc(&c->d_frames, sizeof(FrameState) * kMaxFrames));
+    if (!c->d_frames) HIPCHK(hipMalloc(&c->d_frames, sizeof(FrameState) * kMaxBatch));
     return DIC_OK;
 }
 

@@ -34,7 +34,7 @@ dic_status dic_create(dic_ctx **out, int device, void *hip_stream)
             return DIC_E_DEVICE;
         }
     if (hipHostMalloc(reinterpret_cast<void **>(&c->h_pinned), 64 * sizeof(int32_t)) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void **>(&c->h_stats), sizeof(unsigned long long) * (4 * kMaxFrames + 2)) !=
+        hipHostMalloc(reinterpret_cast<void **>(&c->h_stats), sizeof(unsigned long long) * (4 * kMaxBatch + 2)) !=
             hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&c->h_noalloc), kNoallocStageBytes) != hipSuccess) {
         if (c->h_pinned) (void)hipHostFree(c->h_pinned);
@@ -243,7 +243,7 @@ dic_status check_correlate_args(dic_ctx *c, const dic_image *defs, int32_t nfram
                                 int32_t nseeds, const dic_result *outs)
 {
     if (!c->has_ref) FAIL(DIC_E_STATE, "dic_correlate before dic_set_reference");
-    if (nframes < 1 || nframes > kMaxFrames) FAIL(DIC_E_INVAL, "nframes %d (1..%d)", nframes, kMaxFrames);
+    if (nframes < 1 || nframes > kMaxBatch) FAIL(DIC_E_INVAL, "nframes %d (1..%d)", nframes, kMaxBatch);
     if (!defs || !outs) FAIL(DIC_E_INVAL, "NULL images or results");
     if (nseeds < 1 || !seeds) FAIL(DIC_E_INVAL, "no seeds");
     for (int f = 0; f < nframes; ++f) {
@@ -344,7 +344,8 @@ dic_status run_frames(dic_ctx *c, const dic_image *defs, int nframes, int nseeds
     // for wave k of that group, and the last workgroups of one group's launch share
     // the GPU with the other groups' launches instead of leaving it idle.
     const int nchain = launch_chains(nframes);
-    const int per = nframes / nchain;
+    int off[kMaxChains + 1];
+    for (int g = 0; g <= nchain; ++g) off[g] = g * nframes / nchain;
     for (int g = 1; g < nchain; ++g)
         if (!c->chain_stream[g]) HIPCHK(hipStreamCreateWithFlags(&c->chain_stream[g], hipStreamNonBlocking));
     for (int g = 0; g < nchain && nchain > 1; ++g)
@@ -354,8 +355,8 @@ dic_status run_frames(dic_ctx *c, const dic_image *defs, int nframes, int nseeds
     FrameTable table[kMaxChains];
     std::memset(table, 0, sizeof(table));
     for (int g = 0; g < nchain; ++g) {
-        for (int f = 0; f < per; ++f) table[g].f[f] = hf[g * per + f];
-        table[g].n = per;
+        for (int f = off[g]; f < off[g + 1]; ++f) table[g].f[f - off[g]] = hf[f];
+        table[g].n = off[g + 1] - off[g];
     }
     if (nchain > 1) {
         // the other chains start after the frames' set-up and seeds on the first stream
@@ -410,7 +411,7 @@ dic_status run_frames(dic_ctx *c, const dic_image *defs, int nframes, int nseeds
         // size of the next wave of each chain, summed over its frames
         for (int g = 0; g < nchain; ++g) {
             if (!live[g]) continue;
-            launch_count_wave(d_frames + g * per, per, k, c->d_wave_total + g * tstride, cs[g]);
+            launch_count_wave(d_frames + off[g], off[g + 1] - off[g], k, c->d_wave_total + g * tstride, cs[g]);
             HIPCHK(hipMemcpyAsync(c->h_pinned + g, c->d_wave_total + g * tstride + k, sizeof(int32_t),
                                   hipMemcpyDeviceToHost, cs[g]));
         }
@@ -446,7 +447,7 @@ dic_status run_frames(dic_ctx *c, const dic_image *defs, int nframes, int nseeds
     unsigned long long *hs = c->h_stats;
     for (int f = 0; f < nframes; ++f)
         HIPCHK(hipMemcpyAsync(hs + 4 * f, hf[f].stat, sizeof(unsigned long long) * 4, hipMemcpyDeviceToHost, s));
-    double *sp = reinterpret_cast<double *>(hs + 4 * kMaxFrames);
+    double *sp = reinterpret_cast<double *>(hs + 4 * kMaxBatch);
     HIPCHK(hipMemcpyAsync(sp, hf[nframes - 1].seed_p, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     dic_stats S{};

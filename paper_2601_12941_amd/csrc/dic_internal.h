@@ -29,12 +29,6 @@ inline int lds_pitch(int N, int ts)
     return lp * ts <= 8192 ? lp : ts;
 }
 inline bool window_offsets_fit(int64_t cpitch, int ts) { return 4 * cpitch * ts <= 0x7fffffffLL; }
-// Launch chains of a batched call: groups of frames whose waves run on streams of
-// their own (the frames are independent; only a frame's own waves are ordered).
-// Two halves when the frame count splits into two groups of a multiple of 8 (each
-// group keeps the frame-to-XCD affinity of the wave kernel).
-constexpr int kMaxChains = 4;
-inline int launch_chains(int nframes) { return nframes % 16 == 0 ? 2 : 1; }
 // Frames one batched launch may carry (the frame table travels in the kernel
 // arguments, which hold at most 4 KiB).
 constexpr int kMaxFrames = 32;

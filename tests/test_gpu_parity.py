@@ -62,7 +62,7 @@ def test_repeat_runs_are_bitwise_identical(c1):
         assert np.array_equal(a[k], b[k]), k
 
 
-@pytest.mark.parametrize("nframes", [3, 8, 16, 32])
+@pytest.mark.parametrize("nframes", [3, 8, 16, 32, 40, 64])
 def test_batch_equals_plain(nframes):
     # 8, 16 and 32 frames take the kernel's frame-to-XCD affinity (every 8th frame on
     # one XCD group), 3 frames the plain grid stride; both must give every frame
@@ -76,9 +76,10 @@ def test_batch_equals_plain(nframes):
     plain = [eng.correlate(dic.to_device_image(f), w.seeds) for f in frames]
     batch = eng.correlate_batch([dic.to_device_image(f) for f in frames], w.seeds)
     st = eng.stats()
-    # 16 and 32 frames run as two launch chains of half the frames on two streams;
-    # a second call reuses the frame buffers the first call's chains wrote
-    assert st["frames"] == nframes and st["launch_chains"] == (2 if nframes % 16 == 0 else 1)
+    # 16, 32 and 64 frames, and any count above 32 (one launch carries at most 32),
+    # run as two launch chains of half the frames on two streams; a second call
+    # reuses the frame buffers the first call's chains wrote
+    assert st["frames"] == nframes and st["launch_chains"] == (2 if nframes % 16 == 0 or nframes > 32 else 1)
     again = eng.correlate_batch([dic.to_device_image(f) for f in frames], w.seeds)
     torch.cuda.synchronize()
     for a, b, c in zip(plain, batch, again):
@@ -96,6 +97,6 @@ def test_batch_frame_limit():
     eng.set_reference(dic.to_device_image(pair.ref), torch.from_numpy(pair.roi).cuda(), **w.params())
     d = dic.to_device_image(pair.deformed)
     with pytest.raises(dic.DicError) as e:
-        eng.correlate_batch([d] * 33, w.seeds)
+        eng.correlate_batch([d] * 65, w.seeds)
     assert e.value.code == dic.DIC_E_INVAL
     eng.close()
