@@ -46,6 +46,18 @@ def test_pipelined_blocks_parity(N, shape, tps):
     compare(g, o, npar=shape)
 
 
+@pytest.mark.parametrize("N, tps, tile", [(51, 256, 68), (61, 256, 96), (21, 64, 38)])
+def test_window_sides_and_lds_pitch_parity(N, tps, tile):
+    # windows wider than one 64-lane staging request (68 and 96 samples: two
+    # requests per row), a padded LDS row pitch (68 at N 51 -> 83, 38 at N 21 ->
+    # 53) and a window too large to pad (96 at N 61: pitch 96)
+    w = synth.workload("c3", size=384, N=N, shape=6)
+    pair = w.pair()
+    g, _ = gpu_run(pair, w, threads_per_subset=tps, tile_side=tile)
+    o = oracle_run(pair, w)
+    compare(g, o)
+
+
 @pytest.mark.parametrize("N", [21, 41])
 @pytest.mark.parametrize("shape", [6, 12])
 def test_quadratic_field_parity(N, shape):
