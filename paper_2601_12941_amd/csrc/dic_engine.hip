@@ -338,12 +338,12 @@ dic_status run_frames(dic_ctx *c, const dic_image *defs, int nframes, int nseeds
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(c->ev[2], s));
 
-    const int grid = c->variant ? wave_grid_hint(c->np, 256, c->device) : wave_grid_hint(c->np, c->tps, c->device);
     // Launch chains: the frames are independent, so a batch is split into groups
     // whose waves run on streams of their own.  Wave k + 1 of a group waits only
     // for wave k of that group, and the last workgroups of one group's launch share
     // the GPU with the other groups' launches instead of leaving it idle.
     const int nchain = launch_chains(nframes);
+    const int grid = wave_grid_hint(c->np, c->variant ? 256 : c->tps, c->device, nchain);
     int off[kMaxChains + 1];
     for (int g = 0; g <= nchain; ++g) off[g] = g * nframes / nchain;
     for (int g = 1; g < nchain; ++g)

@@ -162,7 +162,7 @@ void launch_count_wave(const FrameState *F_dev, int nframes, int k, int32_t *out
 void launch_zero32(void *p, int64_t words, hipStream_t s);
 int pixels_per_thread(int N, int T);
 void launch_finalize(const RefView &R, const FrameState &F, int np, bool nan_unconverged, hipStream_t s);
-int wave_grid_hint(int np, int tps, int device);
+int wave_grid_hint(int np, int tps, int device, int chains);
 bool supported_tps(int N, int tps);
 // the variants' wave kernel (rigid shape, NSSD / SSD, Levenberg-Marquardt; dic_variants.hip)
 bool launch_wave_var(const FrameTable &F, int step, int np, int grid, hipStream_t s);

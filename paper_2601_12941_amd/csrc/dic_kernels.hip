@@ -1894,15 +1894,19 @@ bool supported_tps(int N, int tps)
     return P > 0 && !(tps == 64 && P < 4);
 }
 
-int wave_grid_hint(int np, int tps, int device)
+int wave_grid_hint(int np, int tps, int device, int chains)
 {
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-    // enough workgroups to keep every SIMD busy; one-wavefront workgroups take about
-    // two subsets each of a full 32-frame wave, so their uneven run times even out over
-    // many workgroups (64 per compute unit: +2.4 % over 16 with 16 frames per launch,
-    // +2.5 % over 32 with 32 frames; 128 is no faster)
-    const int per_cu = tps <= 64 ? 64 : (tps == 128 ? 8 : 4);
+    // Enough workgroups to keep every SIMD busy.  One launch chain: one-wavefront
+    // workgroups 64 per compute unit take about two subsets each of a full 32-frame
+    // wave, so their uneven run times even out over many workgroups and no slow one
+    // sets the launch time (+2.4 % over 16 with 16 frames per launch, +2.5 % over 32
+    // with 32 frames; 128 is no faster).  Two chains: the other chain's launch fills a
+    // launch's tail, and 8 per compute unit (all resident from the start, each walking
+    // about 8 subsets of a 16-frame wave) is fastest: +4 % over 64, while 4 and 6 leave
+    // SIMDs idle (-9 % and -5 %).
+    const int per_cu = tps <= 64 ? (chains > 1 ? 8 : 64) : (tps == 128 ? 8 : 4);
     (void)np;
     return cus * per_cu;
 }

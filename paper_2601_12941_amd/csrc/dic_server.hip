@@ -492,7 +492,10 @@ dic_status dic_server_step(dic_server *s, int32_t steps)
                 }
                 table.n = static_cast<int>(i1 - i0);
                 const int np = std::get<0>(g.first), tps = std::get<1>(g.first);
-                const int grid = wave_grid_hint(np, tps, s->device);
+                // the one-chain grid even with two chains: the serving launches carry few
+                // subsets per request, and 8 workgroups per compute unit measured slower
+                // there (20 requests/s: p50 291 ms against 256 ms)
+                const int grid = wave_grid_hint(np, tps, s->device, 1);
                 if (!launch_wave(table, s->step, np, nmax, tps, std::get<2>(g.first) != 0, tsmax, ldsmax, grid,
                                  chain_stream[ch])) {
                     if (nchain == 2) {
