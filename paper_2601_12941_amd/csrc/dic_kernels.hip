@@ -155,24 +155,46 @@ constexpr int kFir = 15;
 __constant__ float c_fir[2 * kFir + 1];
 
 constexpr int kRowBlock = 256;
+constexpr int kRowOut = 4;   // consecutive outputs per thread of the row pass
 
+// Rows: a workgroup stages kRowBlock * kRowOut pixels of one row and their
+// 15-pixel halos in LDS; each thread reads its kRowOut + 30 inputs as 16-byte
+// LDS vectors and evaluates its kRowOut outputs from registers, each the same
+// 31-term FMA chain as a direct evaluation.
 __global__ __launch_bounds__(kRowBlock) void k_prefilter_rows(const void *src, int64_t sp, int pixel, int W,
                                                                float *tmp, int64_t tp)
 {
-    __shared__ float s[kRowBlock + 2 * kFir];
+    constexpr int kSpan = kRowBlock * kRowOut;
+    constexpr int kVec = (kRowOut + 2 * kFir + 3) / 4;   // 16-byte reads per thread
+    __shared__ float4 s4[kSpan / 4 + kVec];
+    float *s = reinterpret_cast<float *>(s4);
     const int y = blockIdx.y;
-    const int xb = blockIdx.x * kRowBlock;
-    for (int i = threadIdx.x; i < kRowBlock + 2 * kFir; i += kRowBlock) {
-        const int x = xb - kFir + i;
-        s[i] = load_pixel(src, sp, pixel, fold(x, W), y);
+    const int xb = blockIdx.x * kSpan;
+    if (xb >= kFir && xb + kSpan + kFir <= W) {
+        for (int i = threadIdx.x; i < kSpan + 2 * kFir; i += kRowBlock) s[i] = load_pixel(src, sp, pixel, xb - kFir + i, y);
+    } else {
+        for (int i = threadIdx.x; i < kSpan + 2 * kFir; i += kRowBlock)
+            s[i] = load_pixel(src, sp, pixel, fold(xb - kFir + i, W), y);
     }
     __syncthreads();
-    const int x = xb + threadIdx.x;
-    if (x < W) {
+    float v[4 * kVec];
+#pragma unroll
+    for (int j = 0; j < kVec; ++j) {
+        const float4 q = s4[threadIdx.x * (kRowOut / 4) + j];
+        v[4 * j] = q.x;
+        v[4 * j + 1] = q.y;
+        v[4 * j + 2] = q.z;
+        v[4 * j + 3] = q.w;
+    }
+    const int x0 = xb + threadIdx.x * kRowOut;
+    float *out = tmp + static_cast<int64_t>(y) * tp + x0;
+#pragma unroll
+    for (int r = 0; r < kRowOut; ++r) {
+        if (x0 + r >= W) break;
         float acc = 0.0f;
 #pragma unroll
-        for (int n = -kFir; n <= kFir; ++n) acc = fmaf(c_fir[n + kFir], s[threadIdx.x + kFir - n], acc);
-        tmp[static_cast<int64_t>(y) * tp + x] = acc;
+        for (int n = -kFir; n <= kFir; ++n) acc = fmaf(c_fir[n + kFir], v[r + kFir - n], acc);
+        out[r] = acc;
     }
 }
 
@@ -251,7 +273,7 @@ void launch_prefilter(const void *src, int64_t src_pitch_bytes, int pixel, int W
         (void)hipMemcpyToSymbol(HIP_SYMBOL(c_fir), h, sizeof(h));
         if (dev >= 0 && dev < 64) taps_ready[dev] = true;
     }
-    dim3 g1((W + kRowBlock - 1) / kRowBlock, H);
+    dim3 g1((W + kRowBlock * kRowOut - 1) / (kRowBlock * kRowOut), H);
     k_prefilter_rows<<<g1, kRowBlock, 0, s>>>(src, src_pitch_bytes, pixel, W, tmp, tmp_pitch);
     dim3 g2((W + 2 * kPad + 63) / 64, (H + 4 * kColRows - 1) / (4 * kColRows));
     dim3 g3((W + 2 * kPad + 63) / 64, (2 * kPad + 3) / 4);
