@@ -103,6 +103,7 @@ struct dic_ctx {
     int32_t *d_wave_total = nullptr;   // wave sizes, [kMaxChains][nodes + 130]: one row per launch chain
     hipStream_t chain_stream[kMaxChains] = {};   // launch chains 1.. of batched calls (default priority)
     hipEvent_t chain_ev[kMaxChains] = {};        // fork (0) and join (1..) events of the chains
+    hipEvent_t count_ev[kMaxChains] = {};        // each chain's next-wave size has reached the host
     RefView *d_view = nullptr;   // device copy of view(), read by the wave kernel
     int32_t *h_pinned = nullptr;
     unsigned long long *h_stats = nullptr;  // pinned: 4 counters per frame, then the last frame's seed shift

@@ -33,6 +33,11 @@ dic_status dic_create(dic_ctx **out, int device, void *hip_stream)
             delete c;
             return DIC_E_DEVICE;
         }
+    for (auto &e : c->count_ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            delete c;
+            return DIC_E_DEVICE;
+        }
     if (hipHostMalloc(reinterpret_cast<void **>(&c->h_pinned), 64 * sizeof(int32_t)) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&c->h_stats), sizeof(unsigned long long) * (4 * kMaxBatch + 2)) !=
             hipSuccess ||
@@ -74,6 +79,8 @@ dic_status dic_destroy(dic_ctx *c)
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto &e : c->chunk_ev) (void)hipEventDestroy(e);
+    for (auto &e : c->count_ev)
+        if (e) (void)hipEventDestroy(e);
     for (auto &e : c->chain_ev)
         if (e) (void)hipEventDestroy(e);
     for (auto &q : c->chain_stream)
@@ -376,7 +383,20 @@ dic_status run_frames(dic_ctx *c, const dic_image *defs, int nframes, int nseeds
         }
         return DIC_OK;
     };
-    for (;;) {
+    // Waves go in chunks of 4, 8, ... 64; after a chunk the host reads the size of
+    // every chain's next wave to decide whether to go on.  The first kAhead waves of
+    // the next chunk are launched before that read, so the GPU runs them while the
+    // host waits; a chain whose next wave is empty gets at most kAhead launches that
+    // find no subset and return at once.
+    constexpr int kAhead = 2;
+    bool launched = true;
+    auto launch_range = [&](int g, int k0, int k1) {
+        for (int kk = k0; kk < k1 && launched; ++kk)
+            launched = c->variant ? launch_wave_var(table[g], kk, c->np, grid, cs[g])
+                                  : launch_wave(table[g], kk, c->np, c->prm.subset_size, c->tps, f64, R.ts,
+                                                R.ts * R.lp, grid, cs[g]);
+    };
+    auto chunk_open = [&]() -> dic_status {
         if (chunk_timing) {
             if (static_cast<int>(c->chunk_ev.size()) < 2 * (nchunk + 1)) {
                 hipEvent_t a, b;
@@ -387,17 +407,11 @@ dic_status run_frames(dic_ctx *c, const dic_image *defs, int nframes, int nseeds
             }
             HIPCHK(hipEventRecord(c->chunk_ev[2 * nchunk], s));
         }
-        int kend = k;
-        bool launched = true;
-        for (int g = 0; g < nchain && launched; ++g) {
-            if (!live[g]) continue;
-            int kk = k;
-            for (int j = 0; j < chunk && kk <= c->nodes && launched; ++j, ++kk)
-                launched = c->variant ? launch_wave_var(table[g], kk, c->np, grid, cs[g])
-                                      : launch_wave(table[g], kk, c->np, c->prm.subset_size, c->tps, f64, R.ts,
-                                                    R.ts * R.lp, grid, cs[g]);
-            kend = kk;
-        }
+        return DIC_OK;
+    };
+    // size of wave kk of every live chain, summed over its frames, on its way to the
+    // host; then the chunk's end
+    auto chunk_close = [&](int kk, bool count) -> dic_status {
         if (!launched) {
             // no kernel for these parameters: let the chains' work so far finish on
             // the call's stream before reporting it
@@ -406,14 +420,13 @@ dic_status run_frames(dic_ctx *c, const dic_image *defs, int nframes, int nseeds
             FAIL(DIC_E_UNSUPPORTED, "no kernel for shape %d, %d threads, subset %d", c->np, c->tps,
                  c->prm.subset_size);
         }
-        k = kend;
         HIPCHK(hipGetLastError());
-        // size of the next wave of each chain, summed over its frames
-        for (int g = 0; g < nchain; ++g) {
+        for (int g = 0; g < nchain && count; ++g) {
             if (!live[g]) continue;
-            launch_count_wave(d_frames + off[g], off[g + 1] - off[g], k, c->d_wave_total + g * tstride, cs[g]);
-            HIPCHK(hipMemcpyAsync(c->h_pinned + g, c->d_wave_total + g * tstride + k, sizeof(int32_t),
+            launch_count_wave(d_frames + off[g], off[g + 1] - off[g], kk, c->d_wave_total + g * tstride, cs[g]);
+            HIPCHK(hipMemcpyAsync(c->h_pinned + g, c->d_wave_total + g * tstride + kk, sizeof(int32_t),
                                   hipMemcpyDeviceToHost, cs[g]));
+            HIPCHK(hipEventRecord(c->count_ev[g], cs[g]));
         }
         if (chunk_timing) {
             const dic_status js = join();
@@ -421,15 +434,41 @@ dic_status run_frames(dic_ctx *c, const dic_image *defs, int nframes, int nseeds
             HIPCHK(hipEventRecord(c->chunk_ev[2 * nchunk + 1], s));
         }
         ++nchunk;
+        return DIC_OK;
+    };
+    dic_status st = chunk_open();
+    if (st != DIC_OK) return st;
+    k = static_cast<int>(std::min<int64_t>(chunk, c->nodes + 1));
+    for (int g = 0; g < nchain; ++g) launch_range(g, 0, k);
+    st = chunk_close(k, true);
+    if (st != DIC_OK) return st;
+    for (;;) {
+        const int ahead = static_cast<int>(std::min<int64_t>(k + kAhead, c->nodes + 1));
+        st = chunk_open();
+        if (st != DIC_OK) return st;
         for (int g = 0; g < nchain; ++g)
-            if (live[g]) HIPCHK(hipStreamSynchronize(cs[g]));
+            if (live[g]) launch_range(g, k, ahead);
         bool any = false;
         for (int g = 0; g < nchain; ++g) {
-            if (live[g]) live[g] = c->h_pinned[g] != 0 && k <= c->nodes;
+            if (!live[g]) continue;
+            HIPCHK(hipEventSynchronize(c->count_ev[g]));
+            live[g] = c->h_pinned[g] != 0 && k <= c->nodes;
             any = any || live[g];
         }
-        if (!any) break;
+        if (!any) {
+            // every chain is done: the look-ahead launches found nothing
+            k = std::max(k, ahead);
+            st = chunk_close(k, false);
+            if (st != DIC_OK) return st;
+            break;
+        }
         chunk = std::min(chunk * 2, 64);
+        const int kend = static_cast<int>(std::min<int64_t>(k + chunk, c->nodes + 1));
+        for (int g = 0; g < nchain; ++g)
+            if (live[g]) launch_range(g, ahead, kend);
+        k = std::max(kend, ahead);
+        st = chunk_close(k, true);
+        if (st != DIC_OK) return st;
     }
     {
         const dic_status js = join();
