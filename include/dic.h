@@ -148,7 +148,8 @@ typedef struct {
     double ms_prefilter;    /* device time of the deformed-image prefilter */
     double ms_wave_kernels; /* device time of the chunks of back-to-back wave launches, host gaps excluded */
     int32_t wave_launches;  /* IC-GN wave steps of the last call: one wave kernel launch per step and
-                               launch chain */
+                               launch chain, counting the up to two steps launched ahead of the
+                               host's last wave-size read, which find no subset */
     int32_t launch_chains;  /* streams the wave launches of the last call ran on: a batched call of
                                16, 32, 48 or 64 frames, or of more than 32, runs its two halves as two
                                chains, each frame's waves in order on its chain's stream; otherwise 1 */

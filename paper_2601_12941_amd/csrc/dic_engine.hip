@@ -28,14 +28,21 @@ dic_status dic_create(dic_ctx **out, int device, void *hip_stream)
     dic_ctx *c = new dic_ctx();
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
+    auto drop = [](dic_ctx *d) {
+        for (auto &e : d->ev)
+            if (e) (void)hipEventDestroy(e);
+        for (auto &e : d->count_ev)
+            if (e) (void)hipEventDestroy(e);
+        delete d;
+    };
     for (auto &e : c->ev)
         if (hipEventCreate(&e) != hipSuccess) {
-            delete c;
+            drop(c);
             return DIC_E_DEVICE;
         }
     for (auto &e : c->count_ev)
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-            delete c;
+            drop(c);
             return DIC_E_DEVICE;
         }
     if (hipHostMalloc(reinterpret_cast<void **>(&c->h_pinned), 64 * sizeof(int32_t)) != hipSuccess ||
@@ -44,7 +51,7 @@ dic_status dic_create(dic_ctx **out, int device, void *hip_stream)
         hipHostMalloc(reinterpret_cast<void **>(&c->h_noalloc), kNoallocStageBytes) != hipSuccess) {
         if (c->h_pinned) (void)hipHostFree(c->h_pinned);
         if (c->h_stats) (void)hipHostFree(c->h_stats);
-        delete c;
+        drop(c);
         return DIC_E_DEVICE;
     }
     // the allocation-free entry point's scratch array on this device (looked up
