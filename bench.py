@@ -378,10 +378,10 @@ def summarize_sq(sq_dir, trace_dir, out_md):
     n = len(disp[(kb, "SQ_WAVES")])
     bt = batched_steps(trace_dir)
     avg_us, chains = bt["step_us"], bt["chains"]
-    # workgroups that find no subset exit at once: the subsets of a launch are the
-    # converged subsets the benchmark counts (1 010 025 per frame, 32 frames in
-    # `chains` launch chains, 1020 wave steps)
-    subsets = 1010025 * 32 / 1020.0 / chains
+    # workgroups that find no subset exit at once: the subsets of the profiled step are
+    # the converged subsets the benchmark counts (1 010 025 per frame, 32 frames), over
+    # all `n` dispatches (the look-ahead launches that find no subset included)
+    subsets = 1010025 * 32 / float(n)
     issue = chains * v["SQ_INSTS_VALU"] / (avg_us * 1e-6)
     simd_rate = 256 * 4 * 2.4e9 / 4          # one wave64 VALU instruction per SIMD every 4 clocks
     from paper_2601_12941_amd import build
@@ -396,8 +396,8 @@ def summarize_sq(sq_dir, trace_dir, out_md):
         if c in v:   # wavefronts and busy cycles are per launch, not per subset
             per = "" if c in ("SQ_WAVES", "SQ_BUSY_CYCLES") else "%.1f" % (v[c] / subsets)
             lines.append("| `%s` | %.0f | %s |" % (c, v[c], per))
-    lines += ["", "Subsets per launch: %.1f (1 010 025 per frame, 32 frames in %d launch chains, 1020 wave steps)."
-              % (subsets, chains),
+    lines += ["", "Subsets per launch: %.1f on average (1 010 025 per frame, 32 frames in %d launch chains, %d "
+              "launches)." % (subsets, chains, n),
               "VALU issue over the %.1f us wave step (the union of the %d chains' concurrent launches, kernel trace of "
               "the same build): %.2e instructions/s, %.0f %% of the %.2e that 1024 SIMDs issue at one wave64 "
               "instruction every 4 clocks (2.4 GHz)." % (avg_us, chains, issue, 100.0 * issue / simd_rate, simd_rate),
