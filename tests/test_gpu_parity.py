@@ -88,6 +88,33 @@ def test_batch_equals_plain(nframes):
             assert torch.equal(a[k], c[k]), k
 
 
+def test_batch_chains_that_end_apart_equal_plain():
+    # 16 frames in two launch chains whose frontiers end at different waves: the first
+    # chain's frames are seeded at the centre, the second chain's near a corner (about
+    # twice the waves), so the first chain stops while the second still launches waves
+    # and look-ahead launches; every frame must equal its own plain call
+    import torch
+    from paper_2601_12941_amd import dic
+    w = synth.workload("c1", size=256)
+    ref, frames, roi = synth.noise_frames(w, 16)
+    centre, corner = [(128.0, 128.0, 0.0, 0.0)], [(40.0, 40.0, 0.0, 0.0)]
+    seeds = [centre if f < 8 else corner for f in range(16)]
+    eng = dic.Engine(0)
+    eng.set_reference(dic.to_device_image(ref), torch.from_numpy(roi).cuda(), **w.params())
+    plain, waves = [], []
+    for f, fr in enumerate(frames):
+        plain.append(eng.correlate(dic.to_device_image(fr), seeds[f]))
+        waves.append(eng.stats()["waves"])
+    assert max(waves[8:]) > max(waves[:8]) + 10
+    batch = eng.correlate_batch([dic.to_device_image(f) for f in frames], seeds)
+    st = eng.stats()
+    assert st["launch_chains"] == 2 and st["waves"] == max(waves)
+    torch.cuda.synchronize()
+    for a, b in zip(plain, batch):
+        for k in a:
+            assert torch.equal(a[k], b[k]), k
+
+
 def test_batch_frame_limit():
     import torch
     from paper_2601_12941_amd import dic
