@@ -407,6 +407,48 @@ def summarize_sq(sq_dir, trace_dir, out_md):
     print("wrote", out_md)
 
 
+SQ_STALL_COUNTERS = ["SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY",
+                     "SQ_ACTIVE_INST_ANY", "SQ_ACTIVE_INST_VALU", "SQ_INSTS_VALU"]
+
+
+def summarize_sq_stalls(sq_dir, out_md):
+    """profiles/k_wave_2048_sq_stalls.md: where the batched k_wave's wavefronts spend
+    their cycles (issuing, waiting on memory or LDS, waiting for an issue slot), from
+    one rocprofv3 --pmc pass over SQ_STALL_COUNTERS."""
+    import csv
+    f = next(os.path.join(r, x) for r, _, fs in os.walk(sq_dir) for x in fs if x.endswith("counter_collection.csv"))
+    acc, disp = {}, {}
+    for r in csv.DictReader(open(f)):
+        k = (_short(r["Kernel_Name"]), r["Counter_Name"])
+        acc[k] = acc.get(k, 0.0) + float(r["Counter_Value"])
+        disp.setdefault(k, set()).add(r["Dispatch_Id"])
+    kb = BATCHED_KERNEL
+    tot = {c: acc[(kb, c)] for c in SQ_STALL_COUNTERS if (kb, c) in acc}
+    n = len(disp[(kb, "SQ_WAVES")])
+    subsets = 1010025 * 32.0
+    wc = tot["SQ_WAVE_CYCLES"]
+    from paper_2601_12941_amd import build
+    lines = ["# k_wave on the 2048^2 workload: where the wavefronts' cycles go", "",
+             "Command (rocprofv3 run from /tmp with TMPDIR=/tmp, from the repository root on the MI355X box):", "",
+             "```", "rocprofv3 --pmc " + " ".join(SQ_STALL_COUNTERS) + " -f csv -d <sq> -o run -- python3 " + PMC_BENCH,
+             "```", "",
+             "Summary written by `python bench.py --summarize-sq-stalls <sq>`. Batched form: one step of 32 frames "
+             "in two launch chains, %d dispatches of `%s` (the look-ahead launches included)." % (n, kb), "",
+             "| Counter | total over the step | per subset | share of SQ_WAVE_CYCLES |", "|---|---|---|---|"]
+    for c in SQ_STALL_COUNTERS:
+        if c not in tot:
+            continue
+        share = "%.3f" % (tot[c] / wc) if c.startswith(("SQ_WAIT", "SQ_ACTIVE")) else ""
+        lines.append("| `%s` | %.4g | %.1f | %s |" % (c, tot[c], tot[c] / subsets, share))
+    lines += ["", "SQ_WAVE_CYCLES counts every resident wavefront's cycles; SQ_WAIT_ANY the cycles a wavefront "
+              "waits on an `s_waitcnt` (memory, LDS, scalar loads), SQ_WAIT_INST_ANY those it waits for an "
+              "instruction to issue, SQ_ACTIVE_INST_VALU those it issues VALU work (the SQ's own cycle units: the "
+              "shares, not the absolute counts, are what this table is for). Two wavefronts share each SIMD.", "",
+              "Kernel build at the time of these counters: sha256 `%s`." % build.kernel_build_id()]
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    print("wrote", out_md)
+
+
 def copy_probe(mib=256, reps=3):
     """A device-to-device copy of known size: its FETCH_SIZE / WRITE_SIZE counters
     read `mib` MiB each per dispatch on an exact counter."""
@@ -1040,6 +1082,8 @@ def main():
     ap.add_argument("--summarize-trace", metavar="DIR", help="write the kernel-trace summary of a rocprofv3 run")
     ap.add_argument("--summary-out", default=os.path.join(ROOT, "profiles", "k_wave_2048_kernel_trace.md"))
     ap.add_argument("--trace-log", metavar="LOG", help="--summarize-trace: the profiled run's output (its JSON line)")
+    ap.add_argument("--summarize-sq-stalls", metavar="SQ",
+                    help="write the wave-cycle breakdown of the batched k_wave from a rocprofv3 --pmc run")
     ap.add_argument("--summarize-sq", nargs=2, metavar=("SQ", "TRACE"),
                     help="write the SQ instruction-counter summary from a rocprofv3 --pmc run and a kernel trace")
     ap.add_argument("--summarize-l2", nargs=3, metavar=("BENCH", "COPY", "TRACE"),
@@ -1057,6 +1101,9 @@ def main():
         return
     if args.summarize_sq:
         summarize_sq(*args.summarize_sq, os.path.join(ROOT, "profiles", "k_wave_2048_sq_counters.md"))
+        return
+    if args.summarize_sq_stalls:
+        summarize_sq_stalls(args.summarize_sq_stalls, os.path.join(ROOT, "profiles", "k_wave_2048_sq_stalls.md"))
         return
     if args.summarize_l2:
         summarize_l2(*args.summarize_l2, os.path.join(ROOT, "profiles", "k_wave_2048_l2_counters.md"))
