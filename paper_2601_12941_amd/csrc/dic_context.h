@@ -85,7 +85,7 @@ struct dic_ctx {
 
     float *ref_coef_base = nullptr;
     int64_t cpitch = 0;            // coefficient row pitch (elements)
-    float *pf = nullptr, *pfx = nullptr, *pfy = nullptr;
+    float *pa = nullptr;   // interleaved interpolant and gradient [H][ppitch][3]
     int64_t ppitch = 0;
     double *cache = nullptr;
     int8_t *flag = nullptr;
@@ -131,9 +131,7 @@ struct dic_ctx {
         RefView R;
         R.coef = ref_coef_base + kPad * cpitch + kPad;
         R.cpitch = cpitch;
-        R.pf = pf;
-        R.pfx = pfx;
-        R.pfy = pfy;
+        R.pa = pa;
         R.ppitch = ppitch;
         R.cache = cache;
         R.flag = flag;
@@ -188,9 +186,7 @@ template <typename T> inline void dfree(T *&p)
 inline void free_reference(dic_ctx *c)
 {
     dfree(c->ref_coef_base);
-    dfree(c->pf);
-    dfree(c->pfx);
-    dfree(c->pfy);
+    dfree(c->pa);
     dfree(c->cache);
     dfree(c->flag);
     dfree(c->ref_raw);

@@ -122,12 +122,13 @@ dic_status dic_reference_arrays(dic_ctx *c, float *coef_out, float *f_out, float
     if (coef_out)
         HIPCHK(hipMemcpy2DAsync(coef_out, row, c->ref_coef_base + kPad * c->cpitch + kPad, sizeof(float) * c->cpitch,
                                 row, c->H, hipMemcpyDeviceToDevice, c->stream));
-    const float *src[3] = {c->pf, c->pfx, c->pfy};
     float *dst[3] = {f_out, fx_out, fy_out};
+    const RefView R = c->view();
     for (int a = 0; a < 3; ++a)
-        if (dst[a])
-            HIPCHK(hipMemcpy2DAsync(dst[a], row, src[a], sizeof(float) * c->ppitch, row, c->H,
-                                    hipMemcpyDeviceToDevice, c->stream));
+        if (dst[a]) {
+            launch_ref_component(R, a, dst[a], c->stream);
+            HIPCHK(hipGetLastError());
+        }
     HIPCHK(hipStreamSynchronize(c->stream));
     return DIC_OK;
 }
@@ -183,10 +184,10 @@ dic_status dic_set_reference(dic_ctx *c, const dic_image *ref, const uint8_t *ro
     if (!variant && p.shape == DIC_SHAPE_QUADRATIC && tps == 64 && p.subset_size > 21)
         FAIL(DIC_E_UNSUPPORTED, "quadratic shape with 64 threads is built for subsets up to 21");
     {
-        const int64_t cp = round_up(ref->width + 2 * kPad, 64);
+        const int64_t cp = round_up(ref->width + 2 * kPad, 64), pp = round_up(ref->width, 64);
         const int ts = p.tile_side ? p.tile_side : tile_side(p.subset_size);
-        if (!window_offsets_fit(cp, ts))
-            FAIL(DIC_E_INVAL, "image width %d with a %d-sample window: window offsets exceed 32 bits", ref->width, ts);
+        if (!buffer_offsets_fit(cp, ts, pp, p.subset_size))
+            FAIL(DIC_E_INVAL, "image width %d with a %d-sample window: subset offsets exceed 32 bits", ref->width, ts);
     }
 
     HIPCHK(hipSetDevice(c->device));
@@ -210,9 +211,7 @@ dic_status dic_set_reference(dic_ctx *c, const dic_image *ref, const uint8_t *ro
 
     HIPCHK(hipMalloc(&c->ref_coef_base, c->coef_elems() * sizeof(float)));
     HIPCHK(hipMalloc(&c->tmp, sizeof(float) * c->tpitch * c->H));
-    HIPCHK(hipMalloc(&c->pf, sizeof(float) * c->ppitch * c->H));
-    HIPCHK(hipMalloc(&c->pfx, sizeof(float) * c->ppitch * c->H));
-    HIPCHK(hipMalloc(&c->pfy, sizeof(float) * c->ppitch * c->H));
+    HIPCHK(hipMalloc(&c->pa, sizeof(float) * 3 * c->ppitch * c->H));
     // the general kernel of the variants reduces the reference side per subset: no per-node cache
     if (!variant) HIPCHK(hipMalloc(&c->cache, sizeof(double) * cache_slots(c->np) * c->nodes));
     HIPCHK(hipMalloc(&c->flag, c->nodes));
@@ -227,7 +226,7 @@ dic_status dic_set_reference(dic_ctx *c, const dic_image *ref, const uint8_t *ro
     HIPCHK(hipMemcpyAsync(c->d_view, &R, sizeof(RefView), hipMemcpyHostToDevice, s));
     launch_prefilter(ref->data, ref->pitch_bytes, ref->pixel, c->W, c->H, c->tmp, c->tpitch, const_cast<float *>(R.coef),
                      c->cpitch, false, s);
-    launch_ref_pixels(R, c->pf, c->pfx, c->pfy, s);
+    launch_ref_pixels(R, c->pa, s);
     launch_active(roi_mask_dev, R, c->flag, s);
     if (!variant && !launch_ref_nodes(R, c->np, tps, c->cache, c->flag, s)) {
         HIPCHK(hipStreamSynchronize(s));

@@ -28,7 +28,13 @@ inline int lds_pitch(int N, int ts)
     const int lp = ts + (((N - ts) % 32) + 32) % 32;
     return lp * ts <= 8192 ? lp : ts;
 }
-inline bool window_offsets_fit(int64_t cpitch, int ts) { return 4 * cpitch * ts <= 0x7fffffffLL; }
+// The wave kernel addresses a subset's coefficient window (ts rows of cpitch
+// floats) and its reference rows (N rows of ppitch interleaved 12-byte pixels)
+// with 32-bit buffer offsets from the subset's corner.
+inline bool buffer_offsets_fit(int64_t cpitch, int ts, int64_t ppitch, int N)
+{
+    return 4 * cpitch * ts <= 0x7fffffffLL && 12 * ppitch * N <= 0x7fffffffLL;
+}
 // Frames one batched launch may carry (the frame table travels in the kernel
 // arguments, which hold at most 4 KiB).
 constexpr int kMaxFrames = 32;
@@ -58,10 +64,9 @@ inline int cache_slots(int np) { return 3 + 2 * np + np * (np + 1) / 2; }
 struct RefView {
     const float *coef;   // reference spline coefficients at (0,0) of a padded array
     int64_t cpitch;      // elements per coefficient row
-    const float *pf;     // reference interpolant at every pixel [H][ppitch]
-    const float *pfx;    // its x derivative
-    const float *pfy;    // its y derivative
-    int64_t ppitch;
+    const float *pa;     // per pixel the reference interpolant and its x and y derivatives,
+                         // interleaved: [H][ppitch][3]
+    int64_t ppitch;      // pixels per row of pa
     const double *cache; // [cache_slots][nodes]
     const int8_t *flag;  // per node: -1 inactive, 0 usable, else a NodeStatus
     const void *raw;     // resident copy of the raw reference pixels [H][W]
@@ -144,7 +149,10 @@ static_assert(sizeof(FrameTable) + sizeof(int) <= 4096, "the frame table must fi
 // ---- launchers (dic_kernels.hip) -------------------------------------
 void launch_prefilter(const void *src, int64_t src_pitch_bytes, int pixel, int W, int H, float *tmp,
                       int64_t tmp_pitch, void *dst_at_origin, int64_t dst_pitch, bool half, hipStream_t s);
-void launch_ref_pixels(const RefView &R, float *pf, float *pfx, float *pfy, hipStream_t s);
+void launch_ref_pixels(const RefView &R, float *pa, hipStream_t s);
+// copies component a (0 interpolant, 1 x derivative, 2 y derivative) of the interleaved
+// reference array to out [H][W]
+void launch_ref_component(const RefView &R, int a, float *out, hipStream_t s);
 void launch_active(const uint8_t *roi, const RefView &R, int8_t *flag, hipStream_t s);
 bool launch_ref_nodes(const RefView &R, int np, int tps, double *cache, int8_t *flag, hipStream_t s);
 void launch_init_frame(const RefView &R, const FrameState &F, int np, hipStream_t s);

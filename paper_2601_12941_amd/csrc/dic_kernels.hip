@@ -296,7 +296,7 @@ void launch_prefilter(const void *src, int64_t src_pitch_bytes, int pixel, int W
 // image), then per node the sums the iteration reuses and the inverse of the
 // Gauss-Newton Hessian.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_ref_pixels(RefView R, float *pf, float *pfx, float *pfy)
+__global__ __launch_bounds__(256) void k_ref_pixels(RefView R, float *pa)
 {
     const int x = blockIdx.x * 64 + threadIdx.x;
     const int y = blockIdx.y * 4 + threadIdx.y;
@@ -305,16 +305,30 @@ __global__ __launch_bounds__(256) void k_ref_pixels(RefView R, float *pf, float 
     bspline_w(0.0f, w0, w1, w2, w3);
     bspline_dw(0.0f, d0, d1, d2, d3);
     const float *b = R.coef + static_cast<int64_t>(y - 1) * R.cpitch + (x - 1);
-    const int64_t o = static_cast<int64_t>(y) * R.ppitch + x;
-    pf[o] = interp16(b, R.cpitch, w0, w1, w2, w3, w0, w1, w2, w3);
-    pfx[o] = interp16(b, R.cpitch, d0, d1, d2, d3, w0, w1, w2, w3);
-    pfy[o] = interp16(b, R.cpitch, w0, w1, w2, w3, d0, d1, d2, d3);
+    float *o = pa + 3 * (static_cast<int64_t>(y) * R.ppitch + x);
+    o[0] = interp16(b, R.cpitch, w0, w1, w2, w3, w0, w1, w2, w3);
+    o[1] = interp16(b, R.cpitch, d0, d1, d2, d3, w0, w1, w2, w3);
+    o[2] = interp16(b, R.cpitch, w0, w1, w2, w3, d0, d1, d2, d3);
 }
 
-void launch_ref_pixels(const RefView &R, float *pf, float *pfx, float *pfy, hipStream_t s)
+void launch_ref_pixels(const RefView &R, float *pa, hipStream_t s)
 {
     dim3 g((R.W + 63) / 64, (R.H + 3) / 4);
-    k_ref_pixels<<<g, dim3(64, 4), 0, s>>>(R, pf, pfx, pfy);
+    k_ref_pixels<<<g, dim3(64, 4), 0, s>>>(R, pa);
+}
+
+__global__ __launch_bounds__(256) void k_ref_component(RefView R, int a, float *out)
+{
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    if (x >= R.W || y >= R.H) return;
+    out[static_cast<int64_t>(y) * R.W + x] = R.pa[3 * (static_cast<int64_t>(y) * R.ppitch + x) + a];
+}
+
+void launch_ref_component(const RefView &R, int a, float *out, hipStream_t s)
+{
+    dim3 g((R.W + 63) / 64, (R.H + 3) / 4);
+    k_ref_component<<<g, dim3(64, 4), 0, s>>>(R, a, out);
 }
 
 // A node is active iff all N^2 pixels of its subset are inside the ROI.
@@ -400,7 +414,7 @@ __global__ __launch_bounds__(T) void k_ref_nodes(RefView R, double *cache, int8_
         double sf[1] = {0.0};
 #pragma unroll
         for (int j = 0; j < P; ++j)
-            if (j < L.jmax) sf[0] += static_cast<double>(R.pf[o0 + j * rstep]);
+            if (j < L.jmax) sf[0] += static_cast<double>(R.pa[3 * (o0 + j * rstep)]);
         block_allreduce<T, 1>(sf, red, parity);
         const double fm = sf[0] / n;
         const float fm32 = static_cast<float>(fm);
@@ -413,9 +427,9 @@ __global__ __launch_bounds__(T) void k_ref_nodes(RefView R, double *cache, int8_
 #pragma unroll
         for (int j = 0; j < P; ++j) {
             if (j < L.jmax) {
-                const int64_t o = o0 + j * rstep;
-                const float fb = R.pf[o] - fm32;
-                const float gx = R.pfx[o], gy = R.pfy[o];
+                const float *a = R.pa + 3 * (o0 + j * rstep);
+                const float fb = a[0] - fm32;
+                const float gx = a[1], gy = a[2];
                 const float dyf = fmaf(static_cast<float>(j), dyR, dy0);
                 accumulate<NP>(s, fb, fb, gx, gy, dyf);
                 double J[NP];
@@ -956,9 +970,10 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
         // rows per thread of this subset (a launch may mix subset sizes, P is the
         // largest); uniform across the workgroup
         const int JM = __builtin_amdgcn_readfirstlane((N + L.R - 1) / L.R);
-        // reference intensities and gradients.  Row j of every thread lies at the
-        // uniform address of subset row R j plus a fixed per-thread byte offset, so
-        // the loads take a scalar base and no vector address arithmetic.  Threads past
+        // reference intensities and gradients, interleaved per pixel, so one 12-byte
+        // load per row brings all three.  Row j of every thread lies at the uniform
+        // address of subset row R j plus a fixed per-thread byte offset, so the loads
+        // take a scalar base and no vector address arithmetic.  Threads past
         // the subset's rows (the last row of some threads, all rows of the spare
         // threads) read a row inside the subset instead; the pixel loop weights those
         // entries by zero.
@@ -967,25 +982,21 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
             const int64_t top = static_cast<int64_t>(yc - h) * R.ppitch + (xc - h);
             const int rown = L.jmax > 0 ? L.r0 : 0;
             const int rlast = min(rown + L.R * (JM - 1), N - 1) - L.R * (JM - 1);
-            const int lo = 4 * (rown * static_cast<int>(R.ppitch) + L.c);
-            const int lo_last = 4 * (rlast * static_cast<int>(R.ppitch) + L.c);
-            const int rsb = 4 * L.R * static_cast<int>(R.ppitch);
-            const __amdgpu_buffer_rsrc_t bf =
-                __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(R.pf + top), 0, 0x7fffffff, kBufferWord3);
-            const __amdgpu_buffer_rsrc_t bx =
-                __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(R.pfx + top), 0, 0x7fffffff, kBufferWord3);
-            const __amdgpu_buffer_rsrc_t by =
-                __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(R.pfy + top), 0, 0x7fffffff, kBufferWord3);
+            const int lo = 12 * (rown * static_cast<int>(R.ppitch) + L.c);
+            const int lo_last = 12 * (rlast * static_cast<int>(R.ppitch) + L.c);
+            const int rsb = 12 * L.R * static_cast<int>(R.ppitch);
+            const __amdgpu_buffer_rsrc_t ba =
+                __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(R.pa + 3 * top), 0, 0x7fffffff, kBufferWord3);
 #pragma unroll
             for (int j = 0; j < P; ++j) {
-                if (j < JM - 1) {
-                    fb[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(bf, lo, j * rsb, 0));
-                    gx[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(bx, lo, j * rsb, 0));
-                    gy[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(by, lo, j * rsb, 0));
-                } else if (j == JM - 1) {
-                    fb[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(bf, lo_last, j * rsb, 0));
-                    gx[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(bx, lo_last, j * rsb, 0));
-                    gy[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(by, lo_last, j * rsb, 0));
+                if (j < JM) {
+                    int o = j < JM - 1 ? lo : lo_last;
+                    // opaque to the optimiser, so that +4 and +8 stay constant offsets of
+                    // one address and the three loads merge into one 12-byte load
+                    asm volatile("" : "+v"(o));
+                    fb[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ba, o, j * rsb, 0));
+                    gx[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ba, o + 4, j * rsb, 0));
+                    gy[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ba, o + 8, j * rsb, 0));
                 } else {
                     fb[j] = gx[j] = gy[j] = 0.0f;
                 }
@@ -1433,7 +1444,7 @@ __global__ __launch_bounds__(64) void k_ref_nodes_packed(RefView R, double *cach
         double sf = 0.0;
 #pragma unroll
         for (int j = 0; j < P; ++j)
-            if (valid && j < L.jmax) sf += static_cast<double>(R.pf[o0 + j * rstep]);
+            if (valid && j < L.jmax) sf += static_cast<double>(R.pa[3 * (o0 + j * rstep)]);
         sf = seg_allreduce<LS>(sf);
         const double fm = sf / n;
         const float fm32 = static_cast<float>(fm);
@@ -1446,9 +1457,9 @@ __global__ __launch_bounds__(64) void k_ref_nodes_packed(RefView R, double *cach
 #pragma unroll
         for (int j = 0; j < P; ++j) {
             if (valid && j < L.jmax) {
-                const int64_t o = o0 + j * rstep;
-                const float fb = R.pf[o] - fm32;
-                const float gx = R.pfx[o], gy = R.pfy[o];
+                const float *a = R.pa + 3 * (o0 + j * rstep);
+                const float fb = a[0] - fm32;
+                const float gx = a[1], gy = a[2];
                 const float dyf = fmaf(static_cast<float>(j), dyR, dy0);
                 accumulate<NP>(s, fb, fb, gx, gy, dyf);
                 double J[NP];
@@ -1560,18 +1571,16 @@ __global__ __launch_bounds__(64) void k_wave_packed(const FrameTable frames, int
         {
             const int64_t o0 = static_cast<int64_t>(yc - h + L.r0) * R.ppitch + xc - h + L.c;
             const int64_t rs = static_cast<int64_t>(L.R) * R.ppitch;
-            const float *af = R.pf + o0, *ax = R.pfx + o0, *ay = R.pfy + o0;
+            const float *a = R.pa + 3 * o0;
 #pragma unroll
             for (int j = 0; j < P; ++j) {
                 fb[j] = gx[j] = gy[j] = 0.0f;
                 if (act && j < L.jmax) {
-                    fb[j] = *af;
-                    gx[j] = *ax;
-                    gy[j] = *ay;
+                    fb[j] = a[0];
+                    gx[j] = a[1];
+                    gy[j] = a[2];
                 }
-                af += rs;
-                ax += rs;
-                ay += rs;
+                a += 3 * rs;
             }
         }
         double p[NP];

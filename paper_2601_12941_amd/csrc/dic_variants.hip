@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kVarT) void k_wave_var(const FrameTable frames, int
         const int64_t obase = static_cast<int64_t>(yc - h) * R.ppitch + (xc - h);
         {
             double sf = 0.0;
-            for (int i = t; i < n; i += kVarT) sf += static_cast<double>(R.pf[obase + (i / N) * R.ppitch + i % N]);
+            for (int i = t; i < n; i += kVarT) sf += static_cast<double>(R.pa[3 * (obase + (i / N) * R.ppitch + i % N)]);
             var_block_sum<1>(&sf, red, sums);
         }
         if (t == 0) pub_fm = sums[0] / n;
@@ -214,10 +214,10 @@ __global__ __launch_bounds__(kVarT) void k_wave_var(const FrameTable frames, int
 #pragma unroll
             for (int i = 0; i < NR; ++i) v[i] = 0.0;
             for (int i = t; i < n; i += kVarT) {
-                const int64_t o = obase + (i / N) * R.ppitch + i % N;
-                const double ft = static_cast<double>(R.pf[o] - c32);
+                const float *a = R.pa + 3 * (obase + (i / N) * R.ppitch + i % N);
+                const double ft = static_cast<double>(a[0] - c32);
                 double J[NP];
-                sd_terms<NP, double>(J, R.pfx[o], R.pfy[o], static_cast<double>(i % N - h),
+                sd_terms<NP, double>(J, a[1], a[2], static_cast<double>(i % N - h),
                                      static_cast<double>(i / N - h));
                 v[0] += ft;
                 v[1] += ft * ft;
@@ -309,10 +309,10 @@ __global__ __launch_bounds__(kVarT) void k_wave_var(const FrameTable frames, int
                                                       wx2, wx3, wy0, wy1, wy2, wy3)
                                            : interp16(static_cast<const float *>(F.dcoef) + go, F.dpitch, wx0, wx1,
                                                       wx2, wx3, wy0, wy1, wy2, wy3);
-                    const int64_t o = obase + (i / N) * R.ppitch + i % N;
-                    const float ft = R.pf[o] - c32, gt = g - c32;
+                    const float *a = R.pa + 3 * (obase + (i / N) * R.ppitch + i % N);
+                    const float ft = a[0] - c32, gt = g - c32;
                     float J[NP];
-                    sd_terms<NP, float>(J, R.pfx[o], R.pfy[o], dx, dy);
+                    sd_terms<NP, float>(J, a[1], a[2], dx, dy);
                     v[0] += gt;
                     v[1] = fmaf(gt, gt, v[1]);
                     v[2] = fmaf(ft, gt, v[2]);
