@@ -1337,21 +1337,19 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
 #pragma clang fp contract(fast)
                         double dp[NP];
                         {
-                            int q = 0;
-                            Acc acc[NP];
+                            // lane a < NP forms row a of H^{-1} b (terms in column order) and
+                            // the rows are read back from their lanes; the packed upper
+                            // triangle holds H[r][c], r <= c, at r NP - r (r - 1) / 2 + c - r
+                            const int ra = t < NP ? t : 0;
+                            Acc acc = 0;
 #pragma unroll
-                            for (int a = 0; a < NP; ++a) acc[a] = 0;
+                            for (int c = 0; c < NP; ++c) {
+                                const int r0 = min(ra, c), c0 = max(ra, c);
+                                const int q = r0 * NP - (r0 * (r0 - 1)) / 2 + c0 - r0;
+                                acc += static_cast<Acc>(cache[3 + 2 * NP + q]) * b[c];
+                            }
 #pragma unroll
-                            for (int a = 0; a < NP; ++a)
-#pragma unroll
-                                for (int c = a; c < NP; ++c) {
-                                    const Acc hv = static_cast<Acc>(cache[3 + 2 * NP + q]);
-                                    ++q;
-                                    acc[a] += hv * b[c];
-                                    if (c != a) acc[c] += hv * b[a];
-                                }
-#pragma unroll
-                            for (int a = 0; a < NP; ++a) dp[a] = -static_cast<double>(acc[a]);
+                            for (int a = 0; a < NP; ++a) dp[a] = -static_cast<double>(read_lane(acc, a));
                         }
                         zncc_out = zn;
                         if constexpr (NP == 6) compose_affine(p, dp);
