@@ -62,3 +62,42 @@ def test_multiwindow_float_pixels():
     assert same[ok].mean() >= 0.995
     both = ok & same
     assert np.maximum(np.abs(g["u"] - o["u"]), np.abs(g["v"] - o["v"]))[both].max() <= 5e-3
+
+
+def test_widest_reference_within_32_bit_offsets():
+    """The wave kernel addresses a subset's reference rows (interpolant and gradient
+    interleaved, 12 bytes per pixel) with 32-bit offsets from the subset's corner.
+    A reference whose 31 rows pass 2^31 bytes is refused before any work; one just
+    inside is correlated against itself, so every active subset's rows reach
+    offsets within 4 % of 2^31, and every one of them must converge to exactly
+    zero displacement (an identical deformed subset gives a zero increment, Eq. (5)
+    with p = 0, ZNCC 1)."""
+    import torch
+    N, H, step = 31, 40, 15
+    rng = np.random.default_rng(2601)
+    for W, accepted in ((5_800_000, False), (5_760_000, True)):
+        assert (12 * W * N > 2**31 - 1) != accepted   # both widths are multiples of 64
+        img = torch.from_numpy(rng.integers(0, 256, size=(H, W), dtype=np.uint8)).cuda()
+        eng = dic.Engine(0)
+        try:
+            if not accepted:
+                with pytest.raises(dic.DicError) as e:
+                    eng.set_reference(img, subset_size=N, step=step)
+                assert e.value.code == dic.DIC_E_INVAL
+                continue
+            nx, ny = eng.set_reference(img, subset_size=N, step=step)[:2]
+            assert ny == 1
+            h = (N - 1) // 2
+            seeds = [(h + step * int(i), h, 0.0, 0.0) for i in np.linspace(1, nx - 2, 64)]
+            out = eng.correlate(img, seeds)
+            torch.cuda.synchronize()
+            st = out["status"].cpu().numpy()
+            p = out["p"].cpu().numpy()
+            zn = out["zncc"].cpu().numpy()
+            assert np.all(st == 0)
+            assert np.all(p == 0.0)
+            assert np.all(zn == 1.0)
+        finally:
+            eng.close()
+            del img
+            torch.cuda.empty_cache()
