@@ -1336,7 +1336,7 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
                         {
 #pragma clang fp contract(fast)
                         double dp[NP];
-                        {
+                        if constexpr (T <= 128) {
                             // lane a < NP forms row a of H^{-1} b (terms in column order) and
                             // the rows are read back from their lanes; the packed upper
                             // triangle holds H[r][c], r <= c, at r NP - r (r - 1) / 2 + c - r
@@ -1350,6 +1350,26 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
                             }
 #pragma unroll
                             for (int a = 0; a < NP; ++a) dp[a] = -static_cast<double>(read_lane(acc, a));
+                        } else {
+                            // every lane forms every row, walking the packed triangle once; the
+                            // terms of each row still add in column order, so the result is
+                            // bitwise that of the form above (which, at 256 threads, costs the
+                            // 8-row affine block its third wavefront per SIMD)
+                            int q = 0;
+                            Acc acc[NP];
+#pragma unroll
+                            for (int a = 0; a < NP; ++a) acc[a] = 0;
+#pragma unroll
+                            for (int a = 0; a < NP; ++a)
+#pragma unroll
+                                for (int c = a; c < NP; ++c) {
+                                    const Acc hv = static_cast<Acc>(cache[3 + 2 * NP + q]);
+                                    ++q;
+                                    acc[a] += hv * b[c];
+                                    if (c != a) acc[c] += hv * b[a];
+                                }
+#pragma unroll
+                            for (int a = 0; a < NP; ++a) dp[a] = -static_cast<double>(acc[a]);
                         }
                         zncc_out = zn;
                         if constexpr (NP == 6) compose_affine(p, dp);
