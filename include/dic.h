@@ -166,7 +166,11 @@ dic_status dic_create(dic_ctx **out, int device, void *hip_stream);
  * subset mean and norm, the Gauss-Newton Hessian's inverse and the sums the
  * iteration reuses.  roi_mask_dev: DEVICE uint8 [height][width] (pitch =
  * width), nonzero = inside; NULL = whole image.  A node is active iff all N^2
- * of its pixels are inside.
+ * of its pixels are inside.  DIC_E_INVAL, before any state changes, when the
+ * image is too wide for the 32-bit offsets a subset is addressed with:
+ * 12 * P * N and 4 * Q * T must stay below 2^31, with P = width rounded up to
+ * 64, Q = width + 8 rounded up to 64, N the subset size and T the window side
+ * (about 5.7 M pixels of width at N = 31).
  */
 dic_status dic_set_reference(dic_ctx *c, const dic_image *ref, const uint8_t *roi_mask_dev, const dic_params *prm);
 
