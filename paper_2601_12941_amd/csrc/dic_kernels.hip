@@ -1336,7 +1336,7 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
                         {
 #pragma clang fp contract(fast)
                         double dp[NP];
-                        if constexpr (T <= 128) {
+                        if constexpr (T <= 128 || (NP == 12 && F64)) {
                             // lane a < NP forms row a of H^{-1} b (terms in column order) and
                             // the rows are read back from their lanes; the packed upper
                             // triangle holds H[r][c], r <= c, at r NP - r (r - 1) / 2 + c - r
@@ -1354,7 +1354,9 @@ __global__ __launch_bounds__(T, (wave_occupancy_hint<NP, P>())) void k_wave(cons
                             // every lane forms every row, walking the packed triangle once; the
                             // terms of each row still add in column order, so the result is
                             // bitwise that of the form above (which, at 256 threads, costs the
-                            // 8-row affine block its third wavefront per SIMD)
+                            // 8-row affine block its third wavefront per SIMD; the quadratic
+                            // blocks with FP64 sums run at most two either way and spill less
+                            // with it)
                             int q = 0;
                             Acc acc[NP];
 #pragma unroll
